@@ -1,0 +1,177 @@
+/*
+ * randutv.h -- C ABI of the MI355X (gfx950) implementation of randUTV, the
+ * blocked randomized rank-revealing UTV factorization A = U T V^T of
+ * Martinsson, Quintana-Orti and Heavner (arXiv:1703.00998).
+ *
+ * Conventions shared by every entry point
+ *  - Real matrices, column-major (LAPACK convention) with explicit leading
+ *    dimensions.  All matrix pointers are DEVICE pointers owned by the caller;
+ *    the library never frees caller memory.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL means
+ *    the default stream).  Calls return once the work is enqueued, except
+ *    where stated (the tolerance-based early stop reads one scalar per step
+ *    back to the host).
+ *  - Return status: 0 on success; -i if argument i (1-based) is invalid
+ *    (LAPACK INFO convention); RANDUTV_E_UNSUPPORTED for a valid but
+ *    unimplemented case; RANDUTV_E_WORKSPACE if the workspace is too small;
+ *    RANDUTV_E_SYNC if a cross-workgroup wait exceeded its spin limit;
+ *    RANDUTV_E_HIP - (int)hipError for HIP runtime failures.
+ *  - Only m >= n is supported (the paper's setting for an upper triangular T,
+ *    Section 5); m < n returns RANDUTV_E_UNSUPPORTED.
+ */
+#ifndef RANDUTV_H
+#define RANDUTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RANDUTV_E_UNSUPPORTED (-900)
+#define RANDUTV_E_WORKSPACE (-901)
+#define RANDUTV_E_SYNC (-902)
+#define RANDUTV_E_HIP (-1000)
+
+/* Arithmetic used for the four thin-matrix products that carry almost all of
+ * the flops (sampling Y = (X^T X)^q X^T G, power iteration, and the right and
+ * left trailing updates).  The Householder panels, their compact-WY factors,
+ * the b x b SVDs and the U, V accumulation always run in FP64, and T, U, V
+ * are always stored in FP64.  RANDUTV_FP32: operands rounded to FP32, FP32
+ * MFMA with FP32 accumulation.  RANDUTV_BF16X3: each operand split as
+ * x ~ hi + lo with hi = bf16(x), lo = bf16(x - hi); products hi*hi + hi*lo
+ * + lo*hi on BF16 MFMA with FP32 accumulation. */
+typedef enum {
+  RANDUTV_FP64 = 0,
+  RANDUTV_FP32 = 1,
+  RANDUTV_BF16X3 = 2
+} randutv_prec;
+
+/* Flags of randutv_factor. */
+enum {
+  RANDUTV_FORM_U = 1, /* accumulate U (m x m) */
+  RANDUTV_FORM_V = 2  /* accumulate V (n x n) */
+};
+
+/* Number of randomized steps of Figure "The algorithm randUTV": steps i
+ * (0-based) whose I3 = (i+1)b..m and J3 = (i+1)b..n are both nonempty.
+ * Returns -1 for invalid sizes. */
+int64_t randutv_random_steps(int64_t m, int64_t n, int64_t b);
+
+/* Columns of the packed Gaussian matrix G: b * randutv_random_steps(). */
+int64_t randutv_g_cols(int64_t m, int64_t n, int64_t b);
+
+/* Bytes of device workspace randutv_factor needs for these arguments
+ * (written to *bytes).  Returns a status as above. */
+int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
+                           int prec, unsigned flags, size_t* bytes);
+
+/*
+ * randutv_factor -- blocked randUTV (Figure "The algorithm randUTV", Section
+ * 5.2; single step Section 4; the economic final SVD of the Remark in
+ * Section 4.4).
+ *
+ *  1  m, n     rows and columns of A, m >= n >= 1.
+ *  2  b        block size, 1 <= b <= 256.  m <= 32768.
+ *  3  q        power-iteration count, 0 <= q <= 16.
+ *  4  T, ldt   in: A (m x n).  out: the middle factor T, upper triangular in
+ *              the first k columns, with exact zeros below the diagonal and
+ *              off the diagonal inside each diagonal block; the diagonal is
+ *              >= 0 and descending within each block.  Columns k..n-1 hold
+ *              the unreduced trailing block when the factorization stopped
+ *              early.  ldt >= m.
+ *  5  G, ldg   packed N(0,1) matrix, m x randutv_g_cols(m,n,b): randomized
+ *              step i uses G(0:m-i*b-1, i*b:(i+1)*b-1), i.e. the leading
+ *              m - i*b rows of column block i (the paper draws a fresh
+ *              randn(m - b(i-1), b) each step).  ldg >= m.  May be NULL only
+ *              if randutv_g_cols() == 0.
+ *  6  U, ldu   out (if flags & RANDUTV_FORM_U): m x m orthogonal U.  Else may
+ *              be NULL.  ldu >= m.
+ *  7  V, ldv   out (if flags & RANDUTV_FORM_V): n x n orthogonal V.  Else may
+ *              be NULL.  ldv >= n.
+ *  8  k_stop   > 0: stop after the first step whose column count reaches
+ *              k_stop (k = that multiple of b).  <= 0: no limit.
+ *  9  tol      > 0: stop after the first step with ||T(I3,J3)||_F <=
+ *              tol * ||A||_F (Section 1.1, advantage (ii)); this makes the
+ *              call wait on the stream once per step.  <= 0: no test.
+ * 10  prec     randutv_prec.
+ * 11  flags    RANDUTV_FORM_U | RANDUTV_FORM_V.
+ * 12  work     device workspace of at least randutv_workspace_size() bytes,
+ *              256-byte aligned.  Contents on entry are ignored.
+ * 13  work_bytes
+ * 14  k_out    host pointer, may be NULL: the number of leading columns
+ *              driven to triangular form (min(m,n) unless stopped early).
+ *              When non-NULL the call also waits for the stream and then
+ *              reports RANDUTV_E_SYNC or 1 (a small SVD did not converge);
+ *              with k_out == NULL the call only enqueues (no tol test).
+ * 15  stream
+ *
+ * The small b x b SVDs of all steps are computed after the main loop and
+ * their rotations folded into T, U and V then; left and right
+ * multiplications commute, so the result equals the paper's in-loop order.
+ */
+int randutv_factor(int64_t m, int64_t n, int64_t b, int q,
+                   double* T, int64_t ldt,
+                   const double* G, int64_t ldg,
+                   double* U, int64_t ldu,
+                   double* V, int64_t ldv,
+                   int64_t k_stop, double tol,
+                   int prec, unsigned flags,
+                   void* work, size_t work_bytes,
+                   int64_t* k_out, void* stream);
+
+/* ---- Building blocks of one step (exported for testing and reuse) ---- */
+
+/* Thin-matrix product of the sampling and update stages (Section 1.1 (iii);
+ * Section 5.4): C = alpha * op(A) * op(B) + beta * C, all FP64 column-major in
+ * memory, op(X) = X^T when tX != 0, inner products in `prec` arithmetic.
+ * C is M x N, op(A) is M x K, op(B) is K x N.  work (may be NULL) enables a
+ * split of long K: any size, used up to 8*M*N doubles.  Arguments 1..12 are
+ * validated (-i on error). */
+int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 double* C, int64_t ldc, void* work, size_t work_bytes, void* stream);
+
+/* Unpivoted Householder QR of a tall panel (Section 2.4, eq. unpivQR) in
+ * place, LAPACK dgeqrf layout (R on and above the diagonal, reflector tails
+ * below, unit diagonal implied), reflector scalars tau[nb] (dlarfg
+ * convention), and the upper triangular compact-WY factor Tw (nb x nb, ld
+ * ldtw, zeros below the diagonal) with H_0 H_1 ... H_{nb-1} = I - V Tw V^T
+ * (eq. WYrepresentation).  Requires nb <= Mp <= 32768 and nb <= 256.
+ * work: at least randutv_panel_work_size(nb) bytes, 256-byte aligned. */
+size_t randutv_panel_work_size(int64_t nb);
+int randutv_panel_qr(int64_t Mp, int64_t nb, double* P, int64_t ldp, double* tau, double* Tw,
+                     int64_t ldtw, void* work, size_t work_bytes, void* stream);
+
+/* SVD of `count` small square blocks (Figure "The algorithm randUTV",
+ * [Us, Ds, Vs] = svd(R)): matrix i has size nbs[i] (host array, each
+ * 1..ld, ld <= 1024) and is read from R + i*ld*ld (leading dimension ld);
+ * outputs Us, Vs (same layout) and D + i*ld, singular values descending,
+ * each (u_j, v_j) flipped so the largest-magnitude entry of v_j is positive.
+ * work: at least randutv_small_svd_work_size(count, ld) bytes.  Waits for
+ * completion; returns 1 if some matrix did not converge. */
+size_t randutv_small_svd_work_size(int64_t count, int64_t ld);
+int randutv_small_svd(int64_t count, const int* nbs, int64_t ld, const double* R, double* Us,
+                      double* Vs, double* D, void* work, size_t work_bytes, void* stream);
+
+/* ---- Kernel timing (measurement support) ----
+ * randutv_profile_begin() starts recording HIP events on the launch stream
+ * around each thin GEMM, split-K reduction, panel QR and small-SVD launch of
+ * later calls; randutv_profile_end() waits for them and fills, per kernel
+ * class c < max_classes (names from randutv_profile_class_name(c)), the
+ * summed milliseconds, algorithmic flops (2*M*N*K per GEMM) and launch
+ * counts.  Returns the number of classes filled, or a negative status.  Not
+ * thread-safe; meant for one process-wide measurement at a time. */
+int randutv_profile_begin(void);
+int randutv_profile_end(int max_classes, double* ms, double* flops, int64_t* launches);
+const char* randutv_profile_class_name(int cls);
+
+/* Short text for a status code (static storage). */
+const char* randutv_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RANDUTV_H */

@@ -1,0 +1,95 @@
+// Internal declarations of the gfx950 randUTV library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rutv {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Sub-panel width of the Householder panel kernel (columns factored one at a
+// time between block-reflector updates of the rest of the panel).
+constexpr int kPanelNB = 16;
+// Most workgroups the cooperative panel kernel uses, and most rows one
+// workgroup may own (its sub-panel slice lives in LDS).
+constexpr int kPanelMaxWG = 128;
+constexpr int kPanelMaxRows = 256;
+// Spin limit of cross-workgroup waits: far above any legitimate wait, so a
+// wait that never ends turns into an error instead of a hang.
+constexpr unsigned kSpinLimit = 1u << 20;
+// Largest split-K factor of the thin GEMMs.
+constexpr int kMaxSplitK = 8;
+
+// Arithmetic of the thin-matrix products (values of randutv_prec).
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
+
+// ---------------------------------------------------------------- timing
+enum ProfClass { PC_GEMM_NN, PC_GEMM_TN, PC_GEMM_NT, PC_GEMM_TT, PC_SPLITK, PC_PANEL, PC_SVD,
+                 PC_COUNT };
+bool prof_on();
+int prof_mark(hipStream_t st);  // start event; returns a slot or -1 when off
+void prof_done(hipStream_t st, int slot, int cls, double flops);
+
+// ---------------------------------------------------------------- GEMM
+// C(M x N) = alpha * op(A) * op(B) + beta * C, column-major, op = transpose
+// if ta/tb.  `splitws` (>= kMaxSplitK * M * N doubles, or NULL) enables
+// split-K for long reductions.  The arithmetic of the inner products is set
+// by `prec`; operands and C are FP64 in memory.
+hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
+                double alpha, const double* A, int64_t lda, const double* B,
+                int64_t ldb, double beta, double* C, int64_t ldc,
+                double* splitws, size_t splitws_elems);
+
+// ---------------------------------------------------------------- panel QR
+struct PanelWork {
+  double* part;   // 2 * kPanelMaxWG * kPanelNB  (column-step partials)
+  double* bcast;  // 2 * kPanelNB                (pivot row broadcast)
+  double* bpart;  // kPanelMaxWG * kPanelNB * bmax (block-update partials)
+  double* red;    // kPanelNB * bmax            (reduced block products)
+  unsigned* bar;  // 2 counters                  (grid barrier)
+  int* err;       // 1 flag                      (barrier spin limit hit)
+};
+size_t panel_work_bytes(int bmax);
+void panel_work_carve(void* base, int bmax, PanelWork* w);
+
+// Unpivoted Householder QR of the Mp x nb panel P (in place, LAPACK dgeqrf
+// layout: R on and above the diagonal, reflector tails below), tau[nb], and
+// the upper-triangular compact-WY factor Tw (nb x nb, ld = ldtw) with
+// H_0 ... H_{nb-1} = I - V Tw V^T.
+hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp,
+                    double* tau, double* Tw, int64_t ldtw, const PanelWork& w);
+
+// V (Mp x nb, unit lower trapezoidal, explicit ones and zeros) from the
+// dgeqrf layout in P; R (nb x nb upper triangle, zeros below) to Rout.
+hipError_t panel_extract(hipStream_t st, int Mp, int nb, const double* P, int64_t ldp,
+                         double* V, int64_t ldv, double* Rout, int64_t ldr);
+
+// ---------------------------------------------------------------- small SVD
+// Batched one-sided Jacobi SVD of `count` square matrices R_i (size nb_i,
+// stored at R + i*strideR with leading dimension ld) -> Us_i, D_i, Vs_i.
+// Singular values descending, each (u_j, v_j) sign-normalised so that the
+// largest |v_j| entry is positive.  status[i] = sweeps used, or -1 if not
+// converged.
+// nb_dev: device array of sizes; Wk, Vk: scratch of the same shape as Us.
+hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld,
+                       const double* R, int64_t strideR, double* Us, double* Vs,
+                       int64_t strideUV, double* D, int64_t strideD, double* Wk,
+                       double* Vk, int* status, int max_sweeps);
+
+// ---------------------------------------------------------------- misc
+hipError_t copy_matrix(hipStream_t st, int M, int N, const double* A, int64_t lda,
+                       double* B, int64_t ldb);
+hipError_t set_zero(hipStream_t st, int M, int N, double* A, int64_t lda);
+hipError_t set_identity(hipStream_t st, int M, int N, double* A, int64_t lda);
+// A(0:nb,0:nb) = diag(D) with exact zeros elsewhere in the nb x nb block;
+// rows nb..M-1 of those columns are zeroed too.
+hipError_t set_diag_block(hipStream_t st, int M, int nb, const double* D, double* A,
+                          int64_t lda);
+// out[0] = sum of squares of A (M x N).  `scratch` >= 1024 doubles.
+hipError_t sumsq(hipStream_t st, int M, int N, const double* A, int64_t lda,
+                 double* scratch, double* out);
+
+}  // namespace rutv

@@ -1,0 +1,102 @@
+// Optional per-kernel timing with HIP events recorded on the launch stream
+// around each instrumented kernel (thin GEMMs, split-K reductions, panel QR,
+// small SVDs).  Off unless randutv_profile_begin() was called; not
+// thread-safe (one factorization at a time per process while profiling).
+#include <vector>
+
+#include "../../include/randutv.h"
+#include "common.h"
+
+namespace rutv {
+namespace {
+
+struct Rec {
+  hipEvent_t a, b;
+  int cls;
+  double flops;
+};
+
+bool g_on = false;
+std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+const char* kNames[PC_COUNT] = {"gemm_nn", "gemm_tn", "gemm_nt", "gemm_tt",
+                                "splitk_reduce", "panel_qr", "small_svd"};
+
+}  // namespace
+
+bool prof_on() { return g_on; }
+
+int prof_mark(hipStream_t st) {
+  if (!g_on) return -1;
+  hipEvent_t a = take_event(), b = take_event();
+  if (!a || !b) return -1;
+  if (hipEventRecord(a, st) != hipSuccess) return -1;
+  g_recs.push_back(Rec{a, b, -1, 0.0});
+  return (int)g_recs.size() - 1;
+}
+
+void prof_done(hipStream_t st, int slot, int cls, double flops) {
+  if (slot < 0 || slot >= (int)g_recs.size()) return;
+  Rec& r = g_recs[slot];
+  r.cls = cls;
+  r.flops = flops;
+  (void)hipEventRecord(r.b, st);
+}
+
+}  // namespace rutv
+
+using namespace rutv;
+
+extern "C" {
+
+int randutv_profile_begin(void) {
+  for (auto& r : g_recs) {
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  g_on = true;
+  return 0;
+}
+
+int randutv_profile_end(int max_classes, double* ms, double* flops, int64_t* launches) {
+  g_on = false;
+  const int nc = max_classes < PC_COUNT ? max_classes : PC_COUNT;
+  for (int c = 0; c < nc; ++c) {
+    if (ms) ms[c] = 0.0;
+    if (flops) flops[c] = 0.0;
+    if (launches) launches[c] = 0;
+  }
+  int status = 0;
+  for (auto& r : g_recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) status = RANDUTV_E_HIP;
+    float t = 0.f;
+    if (r.cls >= 0 && r.cls < nc && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      if (ms) ms[r.cls] += t;
+      if (flops) flops[r.cls] += r.flops;
+      if (launches) launches[r.cls] += 1;
+    }
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  return status ? status : nc;
+}
+
+const char* randutv_profile_class_name(int cls) {
+  return cls >= 0 && cls < PC_COUNT ? kNames[cls] : "";
+}
+
+}  // extern "C"

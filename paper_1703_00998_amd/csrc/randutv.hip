@@ -1,0 +1,404 @@
+// randUTV driver and C ABI (Figure "The algorithm randUTV", Section 5.2).
+//
+// Per randomized step i (r0 = i*b, X = T(r0:m, r0:n)):
+//   Y = X^T G_i; q times: Z = X Y, Y = X^T Z            (thin MFMA GEMMs)
+//   Householder QR of Y -> Vh, tau, Tw_V                 (cooperative panel)
+//   T(:, r0:n) <- T(:, r0:n) (I - Vh Tw_V Vh^T)          (all m rows)
+//   V(:, r0:n) likewise                                  (if formed)
+//   Householder QR of T(r0:m, r0:r0+b) -> Uh, Tw_U, R    (cooperative panel)
+//   T(r0:m, r0+b:n) <- (I - Uh Tw_U Uh^T)^T T(...)
+//   U(:, r0:m) <- U(:, r0:m) (I - Uh Tw_U Uh^T)          (if formed)
+//   T(r0:m, r0:r0+b) <- 0, R stashed
+// The last block (I3 or J3 empty) takes the economic path of the Remark on
+// tall SVDs: Householder QR, then the SVD of its square R.
+// The b x b SVDs do not feed later steps: step i's rotations act only on
+// block row i (from the left), block column i (from the right) and columns
+// of U and V that later steps never touch, and left and right
+// multiplications commute.  So all SVDs run batched after the loop, one
+// workgroup each, and their rotations are folded back then.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/randutv.h"
+#include "common.h"
+
+using namespace rutv;
+
+namespace {
+
+constexpr int kMaxB = 256;
+constexpr int kMaxPanelRows = kPanelMaxWG * kPanelMaxRows;
+constexpr int kJacobiSweeps = 60;
+
+struct Layout {
+  size_t Y, Vh, Z, P, Uh, W, W2, C, C2, TwV, TwU, tauV, tauU, Rst, Ust, Vst, D, Jw, Jv, Ftmp,
+      split, nrm, ints, panel, total;
+  size_t split_elems;
+};
+
+inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t num_steps(int64_t m, int64_t n, int64_t b) {
+  return std::min((m + b - 1) / b, (n + b - 1) / b);
+}
+
+Layout make_layout(int64_t m, int64_t n, int64_t b) {
+  Layout L{};
+  const int64_t s = num_steps(m, n, b);
+  const size_t d = sizeof(double);
+  const size_t mb = (size_t)m * b, nb = (size_t)n * b, bb = (size_t)b * b;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = al256(off + bytes);
+    return o;
+  };
+  L.Y = take(nb * d);
+  L.Vh = take(nb * d);
+  L.Z = take(mb * d);
+  L.P = take(mb * d);
+  L.Uh = take(mb * d);
+  L.W = take(mb * d);
+  L.W2 = take(mb * d);
+  L.C = take(nb * d);
+  L.C2 = take(nb * d);
+  L.TwV = take(bb * d);
+  L.TwU = take(bb * d);
+  L.tauV = take(b * d);
+  L.tauU = take(b * d);
+  L.Rst = take(s * bb * d);
+  L.Ust = take(s * bb * d);
+  L.Vst = take(s * bb * d);
+  L.D = take(s * b * d);
+  L.Jw = take(s * bb * d);
+  L.Jv = take(s * bb * d);
+  L.Ftmp = take(std::max(mb, nb) * d);
+  L.split_elems = (size_t)kMaxSplitK * std::max(mb, nb);
+  L.split = take(L.split_elems * d);
+  L.nrm = take(1040 * d);
+  L.ints = take((2 * s + 8) * sizeof(int));
+  L.panel = take(panel_work_bytes((int)b));
+  L.total = off;
+  return L;
+}
+
+__global__ void k_set_ints(int* p, int count, int v, int last) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = (i == count - 1) ? last : v;
+}
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0) p[0] = 0;
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) return RANDUTV_E_HIP - (int)e_; \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int64_t randutv_random_steps(int64_t m, int64_t n, int64_t b) {
+  if (m < 1 || n < 1 || b < 1) return -1;
+  const int64_t s = num_steps(m, n, b);
+  int64_t c = 0;
+  for (int64_t i = 0; i < s; ++i)
+    if (i * b + b < m && i * b + b < n) ++c;
+  return c;
+}
+
+int64_t randutv_g_cols(int64_t m, int64_t n, int64_t b) {
+  const int64_t r = randutv_random_steps(m, n, b);
+  return r < 0 ? -1 : r * b;
+}
+
+int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, unsigned flags,
+                           size_t* bytes) {
+  if (n < 1 || m < 1) return -1;
+  if (m < n) return RANDUTV_E_UNSUPPORTED;
+  if (b < 1 || b > kMaxB) return -3;
+  if (q < 0 || q > 16) return -4;
+  if (prec < 0 || prec > 2) return -5;
+  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -6;
+  if (!bytes) return -7;
+  *bytes = make_layout(m, n, b).total;
+  return 0;
+}
+
+const char* randutv_strerror(int status) {
+  if (status == 0) return "success";
+  if (status == 1) return "a small SVD did not converge within the sweep limit";
+  if (status == RANDUTV_E_UNSUPPORTED) return "unsupported case";
+  if (status == RANDUTV_E_WORKSPACE) return "workspace too small or misaligned";
+  if (status == RANDUTV_E_SYNC) return "cross-workgroup wait exceeded its spin limit";
+  if (status <= RANDUTV_E_HIP) return "HIP runtime error";
+  if (status < 0) return "invalid argument";
+  return "unknown status";
+}
+
+int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt,
+                   const double* G, int64_t ldg, double* U, int64_t ldu, double* V,
+                   int64_t ldv, int64_t k_stop, double tol, int prec, unsigned flags,
+                   void* work, size_t work_bytes, int64_t* k_out, void* stream) {
+  if (m < 1 || n < 1) return -1;
+  if (m < n) return RANDUTV_E_UNSUPPORTED;
+  if (m > kMaxPanelRows || m * n > ((int64_t)1 << 40)) return RANDUTV_E_UNSUPPORTED;
+  if (b < 1 || b > kMaxB) return -2;
+  if (q < 0 || q > 16) return -3;
+  if (!T || ldt < m) return -4;
+  const int64_t gcols = randutv_g_cols(m, n, b);
+  if (gcols > 0 && (!G || ldg < m)) return -5;
+  const bool formU = flags & RANDUTV_FORM_U, formV = flags & RANDUTV_FORM_V;
+  if (formU && (!U || ldu < m)) return -6;
+  if (formV && (!V || ldv < n)) return -7;
+  if (prec < 0 || prec > 2) return -10;
+  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -11;
+  if (!work || ((uintptr_t)work & 255)) return -12;
+  const Layout L = make_layout(m, n, b);
+  if (work_bytes < L.total) return RANDUTV_E_WORKSPACE;
+
+  hipStream_t st = (hipStream_t)stream;
+  char* base = (char*)work;
+  auto dp = [&](size_t off) { return (double*)(base + off); };
+  double *Y = dp(L.Y), *Vh = dp(L.Vh), *Z = dp(L.Z), *P = dp(L.P), *Uh = dp(L.Uh), *W = dp(L.W),
+         *W2 = dp(L.W2), *C = dp(L.C), *C2 = dp(L.C2), *TwV = dp(L.TwV), *TwU = dp(L.TwU),
+         *tauV = dp(L.tauV), *tauU = dp(L.tauU), *Rst = dp(L.Rst), *Ust = dp(L.Ust),
+         *Vst = dp(L.Vst), *Dd = dp(L.D), *Jw = dp(L.Jw), *Jv = dp(L.Jv), *Ftmp = dp(L.Ftmp),
+         *split = dp(L.split), *nrm = dp(L.nrm);
+  const int64_t s = num_steps(m, n, b);
+  int* ints = (int*)(base + L.ints);
+  int* nbs = ints;
+  int* jstatus = ints + s;
+  PanelWork pw;
+  panel_work_carve(base + L.panel, (int)b, &pw);
+  const Prec pr = (Prec)prec;
+  const size_t se = L.split_elems;
+  const int M = (int)m, N = (int)n, B = (int)b;
+
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pw.err);
+  if (formU) HIPCHK(set_identity(st, M, M, U, ldu));
+  if (formV) HIPCHK(set_identity(st, N, N, V, ldv));
+
+  double normA = 0.0;
+  if (tol > 0.0) {
+    HIPCHK(sumsq(st, M, N, T, ldt, nrm + 16, nrm));
+    double h = 0.0;
+    HIPCHK(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    normA = std::sqrt(h);
+  }
+
+  std::vector<int> widths;
+  int64_t k_done = n;
+  for (int64_t i = 0; i < s; ++i) {
+    const int r0 = (int)(i * b);
+    const int Mi = M - r0, Ni = N - r0;
+    double* X = T + r0 + (int64_t)r0 * ldt;
+    if (r0 + B < M && r0 + B < N) {
+      const double* Gi = G + (int64_t)i * b * ldg;
+      // Sampling matrix Y = (X^T X)^q X^T G_i.
+      HIPCHK(gemm(st, pr, true, false, Ni, B, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se));
+      for (int it = 0; it < q; ++it) {
+        HIPCHK(gemm(st, pr, false, false, Mi, B, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se));
+        HIPCHK(gemm(st, pr, true, false, Ni, B, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
+      }
+      // [Vq, ~] = qr(Y)
+      HIPCHK(panel_qr(st, Ni, B, Y, N, tauV, TwV, B, pw));
+      HIPCHK(panel_extract(st, Ni, B, Y, N, Vh, N, nullptr, 0));
+      // T(:, J) = T(:, J) Vq, all m rows.
+      double* TJ = T + (int64_t)r0 * ldt;
+      HIPCHK(gemm(st, pr, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
+      HIPCHK(gemm(st, PREC_FP64, false, false, M, B, B, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
+      HIPCHK(gemm(st, pr, false, true, M, Ni, B, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
+      if (formV) {
+        double* VJ = V + (int64_t)r0 * ldv;
+        HIPCHK(gemm(st, PREC_FP64, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, W, M, split, se));
+        HIPCHK(gemm(st, PREC_FP64, false, false, N, B, B, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
+        HIPCHK(gemm(st, PREC_FP64, false, true, N, Ni, B, -1.0, W2, M, Vh, N, 1.0, VJ, ldv, nullptr, 0));
+      }
+      // [Uq, R] = qr(T([I2,I3], J2))
+      HIPCHK(copy_matrix(st, Mi, B, X, ldt, P, M));
+      HIPCHK(panel_qr(st, Mi, B, P, M, tauU, TwU, B, pw));
+      HIPCHK(panel_extract(st, Mi, B, P, M, Uh, M, Rst + (size_t)i * B * B, B));
+      // T([I2,I3], J3) = Uq^T T([I2,I3], J3)
+      const int Nr = Ni - B;
+      double* XJ3 = X + (int64_t)B * ldt;
+      HIPCHK(gemm(st, pr, true, false, B, Nr, Mi, 1.0, Uh, M, XJ3, ldt, 0.0, C, B, split, se));
+      HIPCHK(gemm(st, PREC_FP64, true, false, B, Nr, B, 1.0, TwU, B, C, B, 0.0, C2, B, nullptr, 0));
+      HIPCHK(gemm(st, pr, false, false, Mi, Nr, B, -1.0, Uh, M, C2, B, 1.0, XJ3, ldt, nullptr, 0));
+      // U(:, [I2,I3]) = U(:, [I2,I3]) Uq
+      if (formU) {
+        double* UI = U + (int64_t)r0 * ldu;
+        HIPCHK(gemm(st, PREC_FP64, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, W, M, split, se));
+        HIPCHK(gemm(st, PREC_FP64, false, false, M, B, B, 1.0, W, M, TwU, B, 0.0, W2, M, nullptr, 0));
+        HIPCHK(gemm(st, PREC_FP64, false, true, M, Mi, B, -1.0, W2, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+      }
+      // T([I2,I3], J2) = [R; 0]; R moves to the stash, the diagonal block is
+      // written from the SVD after the loop.
+      HIPCHK(set_zero(st, Mi, B, X, ldt));
+      widths.push_back(B);
+      bool stop = k_stop > 0 && r0 + B >= k_stop;
+      if (!stop && tol > 0.0) {
+        HIPCHK(sumsq(st, Mi - B, Ni - B, X + B + (int64_t)B * ldt, ldt, nrm + 16, nrm + 1));
+        double h = 0.0;
+        HIPCHK(hipMemcpyAsync(&h, nrm + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        stop = std::sqrt(h) <= tol * normA;
+      }
+      if (stop) {
+        k_done = r0 + B;
+        break;
+      }
+    } else {
+      // Last block: economic SVD via Householder QR of T([I2,I3],[J2,J3]).
+      const int c = Ni;
+      HIPCHK(copy_matrix(st, Mi, c, X, ldt, P, M));
+      HIPCHK(panel_qr(st, Mi, c, P, M, tauU, TwU, B, pw));
+      HIPCHK(panel_extract(st, Mi, c, P, M, Uh, M, Rst + (size_t)i * B * B, B));
+      if (formU) {
+        double* UI = U + (int64_t)r0 * ldu;
+        HIPCHK(gemm(st, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, W, M, split, se));
+        HIPCHK(gemm(st, PREC_FP64, false, false, M, c, c, 1.0, W, M, TwU, B, 0.0, W2, M, nullptr, 0));
+        HIPCHK(gemm(st, PREC_FP64, false, true, M, Mi, c, -1.0, W2, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+      }
+      HIPCHK(set_zero(st, Mi, c, X, ldt));
+      widths.push_back(c);
+      k_done = n;
+    }
+  }
+
+  // Batched SVDs of the stashed R blocks, then fold the rotations back:
+  // T(I2,J2) = Ds, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) = T(I1,J2) Vs,
+  // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.
+  const int nsvd = (int)widths.size();
+  hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(256), 0, st, nbs, nsvd, B, widths.back());
+  HIPCHK(batched_svd(st, nsvd, nbs, B, Rst, (int64_t)B * B, Ust, Vst, (int64_t)B * B, Dd, B, Jw, Jv,
+                     jstatus, kJacobiSweeps));
+  for (int i = 0; i < nsvd; ++i) {
+    const int r0 = i * B, w = widths[i];
+    const double* Us = Ust + (size_t)i * B * B;
+    const double* Vs = Vst + (size_t)i * B * B;
+    double* X = T + r0 + (int64_t)r0 * ldt;
+    HIPCHK(set_diag_block(st, w, w, Dd + (size_t)i * B, X, ldt));
+    const int nr = N - r0 - w;
+    if (nr > 0) {
+      double* blk = X + (int64_t)w * ldt;
+      HIPCHK(gemm(st, PREC_FP64, true, false, w, nr, w, 1.0, Us, B, blk, ldt, 0.0, Ftmp, w, nullptr, 0));
+      HIPCHK(copy_matrix(st, w, nr, Ftmp, w, blk, ldt));
+    }
+    if (r0 > 0) {
+      double* blk = T + (int64_t)r0 * ldt;
+      HIPCHK(gemm(st, PREC_FP64, false, false, r0, w, w, 1.0, blk, ldt, Vs, B, 0.0, Ftmp, r0, nullptr, 0));
+      HIPCHK(copy_matrix(st, r0, w, Ftmp, r0, blk, ldt));
+    }
+    if (formU) {
+      double* blk = U + (int64_t)r0 * ldu;
+      HIPCHK(gemm(st, PREC_FP64, false, false, M, w, w, 1.0, blk, ldu, Us, B, 0.0, Ftmp, M, nullptr, 0));
+      HIPCHK(copy_matrix(st, M, w, Ftmp, M, blk, ldu));
+    }
+    if (formV) {
+      double* blk = V + (int64_t)r0 * ldv;
+      HIPCHK(gemm(st, PREC_FP64, false, false, N, w, w, 1.0, blk, ldv, Vs, B, 0.0, Ftmp, N, nullptr, 0));
+      HIPCHK(copy_matrix(st, N, w, Ftmp, N, blk, ldv));
+    }
+  }
+  if (k_out) {
+    *k_out = k_done;
+    HIPCHK(hipStreamSynchronize(st));
+    int err = 0;
+    HIPCHK(hipMemcpy(&err, pw.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) return RANDUTV_E_SYNC;
+    std::vector<int> js(nsvd);
+    HIPCHK(hipMemcpy(js.data(), jstatus, nsvd * sizeof(int), hipMemcpyDeviceToHost));
+    for (int v : js)
+      if (v < 0) return 1;
+  }
+  return 0;
+}
+
+
+int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 double* C, int64_t ldc, void* work, size_t work_bytes, void* stream) {
+  if (prec < 0 || prec > 2) return -1;
+  if (M < 0 || M > INT32_MAX) return -4;
+  if (N < 0 || N > INT32_MAX) return -5;
+  if (K < 0 || K > INT32_MAX) return -6;
+  const int64_t arows = ta ? K : M, brows = tb ? N : K;
+  if (M > 0 && N > 0 && K > 0) {
+    if (!A || lda < std::max<int64_t>(1, arows)) return -8;
+    if (!B || ldb < std::max<int64_t>(1, brows)) return -10;
+  }
+  if (M > 0 && N > 0 && (!C || ldc < M)) return -13;
+  hipError_t e = gemm((hipStream_t)stream, (Prec)prec, ta != 0, tb != 0, (int)M, (int)N, (int)K,
+                      alpha, A, lda, B, ldb, beta, C, ldc, (double*)work,
+                      work ? work_bytes / sizeof(double) : 0);
+  return e == hipSuccess ? 0 : RANDUTV_E_HIP - (int)e;
+}
+
+size_t randutv_panel_work_size(int64_t nb) {
+  return nb < 1 || nb > kMaxB ? 0 : panel_work_bytes((int)nb);
+}
+
+int randutv_panel_qr(int64_t Mp, int64_t nb, double* P, int64_t ldp, double* tau, double* Tw,
+                     int64_t ldtw, void* work, size_t work_bytes, void* stream) {
+  if (Mp < 1 || Mp > kMaxPanelRows) return -1;
+  if (nb < 1 || nb > kMaxB || nb > Mp) return -2;
+  if (!P || ldp < Mp) return -3;
+  if (!tau) return -5;
+  if (!Tw || ldtw < nb) return -6;
+  if (!work || ((uintptr_t)work & 255) || work_bytes < panel_work_bytes((int)nb)) return -8;
+  PanelWork pw;
+  panel_work_carve(work, (int)nb, &pw);
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pw.err);
+  hipError_t e = panel_qr(st, (int)Mp, (int)nb, P, ldp, tau, Tw, ldtw, pw);
+  if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
+  int err = 0;
+  e = hipMemcpy(&err, pw.err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
+  return err ? RANDUTV_E_SYNC : 0;
+}
+
+size_t randutv_small_svd_work_size(int64_t count, int64_t ld) {
+  if (count < 1 || ld < 1 || ld > 1024) return 0;
+  return al256((size_t)2 * count * ld * ld * sizeof(double)) + al256(2 * count * sizeof(int));
+}
+
+int randutv_small_svd(int64_t count, const int* nbs, int64_t ld, const double* R, double* Us,
+                      double* Vs, double* D, void* work, size_t work_bytes, void* stream) {
+  if (count < 1) return -1;
+  if (!nbs) return -2;
+  if (ld < 1 || ld > 1024) return -3;
+  for (int64_t i = 0; i < count; ++i)
+    if (nbs[i] < 1 || nbs[i] > ld) return -2;
+  if (!R) return -4;
+  if (!Us) return -5;
+  if (!Vs) return -6;
+  if (!D) return -7;
+  const size_t need = randutv_small_svd_work_size(count, ld);
+  if (!work || ((uintptr_t)work & 255) || work_bytes < need) return -8;
+  hipStream_t st = (hipStream_t)stream;
+  double* Jw = (double*)work;
+  double* Jv = Jw + (size_t)count * ld * ld;
+  int* ints = (int*)((char*)work + al256((size_t)2 * count * ld * ld * sizeof(double)));
+  hipError_t e = hipMemcpyAsync(ints, nbs, count * sizeof(int), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = batched_svd(st, (int)count, ints, (int)ld, R, ld * ld, Us, Vs, ld * ld, D, ld, Jw, Jv,
+                    ints + count, kJacobiSweeps);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
+  std::vector<int> js(count);
+  e = hipMemcpy(js.data(), ints + count, count * sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
+  for (int v : js)
+    if (v < 0) return 1;
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/randutv.h, and validates arguments before touching the
+GPU (LAPACK-style -i statuses).  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "randutv.h")
+LIB = os.path.join(ROOT, "paper_1703_00998_amd", "librandutv.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(randutv_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    from paper_1703_00998_amd import binding
+    return binding.lib()
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared()
+    for n in ["randutv_factor", "randutv_workspace_size", "randutv_g_cols",
+              "randutv_random_steps", "randutv_gemm", "randutv_panel_qr",
+              "randutv_small_svd", "randutv_strerror"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_names_match_header(lib):
+    from paper_1703_00998_amd import binding
+    assert set(binding.EXPORTS) <= set(_declared())
+
+
+def test_step_counts(lib):
+    # Figure randUTV: s = min(ceil(m/b), ceil(n/b)); randomized iff I3, J3 nonempty.
+    assert lib.randutv_random_steps(500, 500, 32) == 15
+    assert lib.randutv_g_cols(500, 500, 32) == 480
+    assert lib.randutv_g_cols(8000, 8000, 256) == 7936
+    assert lib.randutv_random_steps(4000, 4000, 128) == 31
+    assert lib.randutv_random_steps(50, 40, 64) == 0
+    assert lib.randutv_random_steps(20000, 5000, 128) == 39
+    assert lib.randutv_random_steps(0, 5, 2) == -1
+
+
+def test_workspace_and_argument_validation(lib):
+    sz = ctypes.c_size_t(0)
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 3, ctypes.byref(sz)) == 0
+    assert sz.value > 0
+    assert lib.randutv_workspace_size(80, 100, 16, 1, 0, 3, ctypes.byref(sz)) == -900
+    assert lib.randutv_workspace_size(100, 80, 0, 1, 0, 3, ctypes.byref(sz)) == -3
+    assert lib.randutv_workspace_size(100, 80, 16, -1, 0, 3, ctypes.byref(sz)) == -4
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 7, 3, ctypes.byref(sz)) == -5
+    vp = ctypes.c_void_p
+    null = vp(0)
+    fake = vp(1 << 20)  # never dereferenced: validation fails first
+    args = dict(m=100, n=80, b=16, q=1, T=fake, ldt=100, G=fake, ldg=100, U=null, ldu=100,
+                V=null, ldv=80, k_stop=0, tol=0.0, prec=0, flags=0, work=null, wb=0,
+                k=None, st=null)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return lib.randutv_factor(a["m"], a["n"], a["b"], a["q"], a["T"], a["ldt"], a["G"],
+                                  a["ldg"], a["U"], a["ldu"], a["V"], a["ldv"], a["k_stop"],
+                                  a["tol"], a["prec"], a["flags"], a["work"], a["wb"],
+                                  a["k"], a["st"])
+    assert call(m=0) == -1
+    assert call(m=50) == -900          # m < n unsupported
+    assert call(b=0) == -2
+    assert call(b=1000) == -2
+    assert call(q=-1) == -3
+    assert call(T=null) == -4
+    assert call(ldt=99) == -4
+    assert call(G=null) == -5
+    assert call(ldg=10) == -5
+    assert call(flags=1) == -6         # U requested but NULL
+    assert call(flags=2) == -7
+    assert call(prec=3) == -10
+    assert call(flags=8) == -11
+    assert call() == -12               # no workspace
+    assert call(work=vp(4096 + 8)) == -12   # misaligned
+    assert call(work=vp(4096), wb=16) == -901
+    assert lib.randutv_strerror(-900) == b"unsupported case"
+
+
+def test_gemm_and_panel_validation(lib):
+    vp = ctypes.c_void_p
+    f = vp(1 << 20)
+    assert lib.randutv_gemm(9, 0, 0, 4, 4, 4, 1.0, f, 4, f, 4, 0.0, f, 4, vp(0), 0, vp(0)) == -1
+    assert lib.randutv_gemm(0, 0, 0, 4, 4, 4, 1.0, f, 3, f, 4, 0.0, f, 4, vp(0), 0, vp(0)) == -8
+    assert lib.randutv_gemm(0, 1, 0, 4, 4, 5, 1.0, f, 4, f, 5, 0.0, f, 4, vp(0), 0, vp(0)) == -8
+    assert lib.randutv_gemm(0, 0, 0, 4, 4, 4, 1.0, f, 4, f, 4, 0.0, f, 3, vp(0), 0, vp(0)) == -13
+    assert lib.randutv_panel_qr(10, 20, f, 10, f, f, 20, f, 1 << 30, vp(0)) == -2
+    assert lib.randutv_panel_qr(100, 300, f, 100, f, f, 300, f, 1 << 30, vp(0)) == -2
+    assert lib.randutv_panel_qr(100, 8, f, 99, f, f, 8, f, 1 << 30, vp(0)) == -3
+    assert lib.randutv_panel_work_size(0) == 0

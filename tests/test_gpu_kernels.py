@@ -1,0 +1,166 @@
+"""GPU unit tests of the building blocks behind the C ABI: the MFMA thin GEMM,
+the cooperative Householder panel QR with its compact-WY factor, and the
+batched small SVD.  References are independent (numpy / LAPACK via scipy,
+run on the host)."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_00998_amd import binding
+    binding.lib()
+    return binding
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+GEMM_SHAPES = [(64, 64, 16), (100, 70, 130), (257, 33, 1500), (8, 300, 7), (1, 1, 1),
+               (130, 256, 4100), (33, 17, 0)]
+
+
+@pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm_fp64_matches_numpy(B, M, N, K, ta, tb):
+    """Thin product C = alpha op(A) op(B) + beta C (Section 5.4's BLAS-3 work):
+    FP64 MFMA result within a few ulps * K of the FP64 numpy product,
+    including ragged tiles and split-K."""
+    print(f"gemm fp64 M={M} N={N} K={K} ta={ta} tb={tb}", flush=True)
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    Bm = rng.standard_normal((N, K) if tb else (K, N))
+    C0 = rng.standard_normal((M, N))
+    ref = 0.75 * ((A.T if ta else A) @ (Bm.T if tb else Bm)) - 0.5 * C0
+    dA, dB, dC = B.colmajor(A), B.colmajor(Bm), B.colmajor(C0)
+    ws = B.workspace(8 * M * N * 8)
+    B.randutv_gemm(dC, dA, dB, ta=ta, tb=tb, alpha=0.75, beta=-0.5, work=ws)
+    torch.cuda.synchronize()
+    got = _np(dC)
+    scale = np.sqrt(max(K, 1)) * 1e-15 * 10
+    np.testing.assert_allclose(got, ref, rtol=0, atol=scale * (np.abs(ref).max() + 1))
+
+
+def _larft(V, tau):
+    """Host reference compact-WY factor by the column recurrence
+    T(0:j,j) = -tau_j T(0:j,0:j) V(:,0:j)^T v_j, T(j,j) = tau_j."""
+    nb = tau.size
+    T = np.zeros((nb, nb))
+    for j in range(nb):
+        T[:j, j] = -tau[j] * (T[:j, :j] @ (V[:, :j].T @ V[:, j]))
+        T[j, j] = tau[j]
+    return T
+
+
+@pytest.mark.parametrize("Mp,nb", [(40, 7), (300, 32), (1000, 64), (257, 256), (5000, 256),
+                                   (8000, 256), (129, 128), (20000, 128), (64, 64), (17, 1)])
+def test_panel_qr_matches_lapack(B, Mp, nb):
+    """Unpivoted Householder QR (Section 2.4 eq. unpivQR) against LAPACK dgeqrf
+    (same dlarfg convention): R, tau and reflector tails; the compact-WY factor
+    against the host recurrence, and I - V Tw V^T against dorgqr's Q."""
+    print(f"panel Mp={Mp} nb={nb}", flush=True)
+    rng = np.random.default_rng(Mp + nb)
+    A = rng.standard_normal((Mp, nb))
+    if nb >= 8:
+        A[:, 3] *= 1e-6  # graded columns
+    qr, tau_ref, _, info = scipy.linalg.lapack.dgeqrf(np.asfortranarray(A))
+    assert info == 0
+    dP = B.colmajor(A)
+    dtau = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    dTw = B.colmajor(np.full((nb, nb), np.nan))
+    B.randutv_panel_qr(dP, dtau, dTw)
+    torch.cuda.synchronize()
+    P, tau, Tw = _np(dP), _np(dtau), _np(dTw)
+    nA = np.linalg.norm(A)
+    np.testing.assert_allclose(np.triu(P[:nb]), np.triu(qr[:nb]), rtol=0, atol=1e-13 * nA)
+    np.testing.assert_allclose(tau, tau_ref, rtol=0, atol=1e-13)
+    V = np.tril(P, -1)[:, :nb] + np.eye(Mp, nb)
+    Vref = np.tril(qr, -1)[:, :nb] + np.eye(Mp, nb)
+    np.testing.assert_allclose(V, Vref, rtol=0, atol=1e-11)
+    assert np.all(np.tril(Tw, -1) == 0.0)
+    Tref = _larft(V, tau)
+    np.testing.assert_allclose(Tw, Tref, rtol=0, atol=1e-12 * (np.abs(Tref).max() + 1))
+    Q = np.eye(Mp, nb) - V @ (Tw @ V[:nb, :].T)
+    Qref = scipy.linalg.lapack.dorgqr(qr, tau_ref)[0][:, :nb]
+    np.testing.assert_allclose(Q, Qref, rtol=0, atol=1e-12)
+
+
+def test_panel_qr_zero_and_rank_deficient(B):
+    """tau = 0 when the part below the diagonal is zero (dlarfg), also with a
+    negative diagonal entry; exact-zero columns give identity reflectors."""
+    Mp, nb = 300, 16
+    A = np.zeros((Mp, nb))
+    A[0, 0] = -2.0
+    rng = np.random.default_rng(1)
+    A[:, 5] = rng.standard_normal(Mp)
+    A[:, 9] = rng.standard_normal(Mp)
+    qr, tau_ref, _, _ = scipy.linalg.lapack.dgeqrf(np.asfortranarray(A))
+    dP = B.colmajor(A)
+    dtau = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    dTw = B.colmajor(np.zeros((nb, nb)))
+    B.randutv_panel_qr(dP, dtau, dTw)
+    torch.cuda.synchronize()
+    tau = _np(dtau)
+    assert tau[0] == 0.0 and _np(dP)[0, 0] == -2.0
+    np.testing.assert_allclose(tau, tau_ref, atol=1e-14)
+    assert np.all(np.isfinite(_np(dP))) and np.all(np.isfinite(_np(dTw)))
+
+
+def _stack(mats, ld):
+    out = np.zeros((len(mats), ld, ld))
+    for i, M in enumerate(mats):
+        n = M.shape[0]
+        out[i, :n, :n] = M.T  # [i] holds the column-major storage (transpose)
+    return torch.as_tensor(out, device="cuda")
+
+
+def test_small_svd_matches_numpy(B):
+    """[Us, Ds, Vs] = svd(R) of Figure randUTV: singular values against LAPACK,
+    Us diag(D) Vs^T = R, orthogonality, canonical signs."""
+    rng = np.random.default_rng(4)
+    sizes = [1, 2, 5, 32, 33, 64, 128, 256]
+    mats = [np.triu(rng.standard_normal((n, n))) for n in sizes]
+    mats[3] = mats[3] * np.exp(-np.arange(32) / 4.0)  # graded columns
+    ld = 256
+    R = _stack(mats, ld)
+    Us, D, Vs, st = B.randutv_small_svd(R, sizes)
+    torch.cuda.synchronize()
+    assert st == 0
+    for i, (n, M) in enumerate(zip(sizes, mats)):
+        u = _np(Us[i]).T[:n, :n]
+        v = _np(Vs[i]).T[:n, :n]
+        d = _np(D[i])[:n]
+        s = np.linalg.svd(M, compute_uv=False)
+        np.testing.assert_allclose(d, s, rtol=1e-13 * n, atol=1e-15 * s[0])
+        np.testing.assert_allclose(u @ np.diag(d) @ v.T, M, atol=1e-13 * s[0] * np.sqrt(n))
+        assert np.linalg.norm(u.T @ u - np.eye(n)) < 1e-13 * n
+        assert np.linalg.norm(v.T @ v - np.eye(n)) < 1e-13 * n
+        for j in range(n):
+            assert v[np.argmax(np.abs(v[:, j])), j] > 0
+
+
+def test_small_svd_zero_and_rank_deficient(B):
+    """Zero singular values: Us is completed to an orthogonal matrix."""
+    n = 24
+    rng = np.random.default_rng(9)
+    Z = np.zeros((n, n))
+    L = rng.standard_normal((n, 3)) @ rng.standard_normal((3, n))
+    R = _stack([Z, np.triu(L)], n)
+    Us, D, Vs, st = B.randutv_small_svd(R, [n, n])
+    torch.cuda.synchronize()
+    assert st == 0
+    for i, M in enumerate([Z, np.triu(L)]):
+        u = _np(Us[i]).T
+        v = _np(Vs[i]).T
+        d = _np(D[i])
+        assert np.linalg.norm(u.T @ u - np.eye(n)) < 1e-12
+        assert np.linalg.norm(v.T @ v - np.eye(n)) < 1e-12
+        np.testing.assert_allclose(u @ np.diag(d) @ v.T, M, atol=1e-12 * (np.abs(M).max() + 1))
