@@ -15,7 +15,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kPanelNB = 16;
 // Most workgroups the cooperative panel kernel uses, and most rows one
 // workgroup may own (its sub-panel slice lives in LDS).
-constexpr int kPanelMaxWG = 128;
+constexpr int kPanelMaxWG = 256;
+constexpr int kPanelMaxWGGlobal = 128;
 constexpr int kPanelMaxRows = 256;
 // Spin limit of cross-workgroup waits: far above any legitimate wait, so a
 // wait that never ends turns into an error instead of a hang.

@@ -294,6 +294,265 @@ __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// LDS-resident variant (used whenever the slabs fit): each workgroup keeps
+// its whole row slab of the panel (all nb columns) in LDS for the entire
+// factorization, so the only global traffic is the initial load, the final
+// write-back and the small cross-slab reduction partials, which are written
+// and read with device-coherent (agent-scope) accesses.
+struct PanelArgs2 {
+  int Mp, nb, nwg, chunk, ldS;
+  double* P;
+  int64_t ldp;
+  double* tau;
+  double* Tw;
+  int64_t ldtw;
+  double* part;
+  double* bcast;
+  double* bpart;
+  double* red;
+  unsigned* bar;
+  int* err;
+};
+
+__device__ inline void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier whose agent-scope release/acquire fences are issued by one
+// wave only (the workgroup barriers order the other waves around it).
+__device__ void grid_sync_lean(unsigned* bar, unsigned nwg, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0 && nwg > 1) {
+    fence_release();
+    const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == nwg - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned it = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if (++it > kSpinLimit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    fence_acquire();
+  }
+  __syncthreads();
+}
+
+constexpr int kFixedLdsDoubles(int nb) { return PNB * nb + PNB * PNB + 2 * nb + 3 * PNB + 8; }
+
+__global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x;
+  const int w = blockIdx.x;
+  const int nwg = a.nwg, nb = a.nb, Mp = a.Mp, ldS = a.ldS;
+  const int rb = w * a.chunk;
+  const int re = min(Mp, rb + a.chunk);
+  const int nrows = max(0, re - rb);
+  double* S = smem;                        // column j of my slab at S + j*ldS
+  double* sred = S + (size_t)nb * ldS;     // [t*nb + j]
+  double* sTs = sred + PNB * nb;           // [i*PNB + t]
+  double* stau = sTs + PNB * PNB;          // [nb]
+  double* srowTw = stau + nb;              // [nb]
+  double* sg = srowTw + nb;
+  double* srow = sg + PNB;
+  double* sw = srow + PNB;
+  double* shh = sw + PNB;
+  const int64_t ldp = a.ldp;
+
+  for (int idx = tid; idx < nb * nrows; idx += 256) {
+    const int j = idx / nrows, rl = idx % nrows;
+    S[j * ldS + rl] = a.P[rb + rl + (int64_t)j * ldp];
+  }
+  __syncthreads();
+  int colstep = 0;
+  for (int c0 = 0; c0 < nb; c0 += PNB) {
+    const int pw = min(PNB, nb - c0);
+    for (int cc = 0; cc < pw; ++cc, ++colstep) {
+      const int c = c0 + cc;
+      const int buf = colstep & 1;
+      double* part = a.part + buf * (kPanelMaxWG * PNB);
+      double* bcast = a.bcast + buf * PNB;
+      const double* xc = S + c * ldS;
+      {
+        const int j = tid >> 4, li = tid & 15;
+        double s = 0.0;
+        if (j >= cc && j < pw) {
+          const double* pj = S + (c0 + j) * ldS;
+          for (int rl = li; rl < nrows; rl += 16)
+            if (rb + rl > c) s += xc[rl] * pj[rl];
+        }
+        s = sum16(s);
+        if (li == 0 && j >= cc && j < pw) st_coh(&part[w * PNB + j], s);
+        if (c >= rb && c < re && tid < pw) st_coh(&bcast[tid], S[(c0 + tid) * ldS + (c - rb)]);
+      }
+      grid_sync_lean(a.bar, nwg, a.err);
+      {
+        const int j = tid >> 4, li = tid & 15;
+        double s = 0.0;
+        if (j >= cc && j < pw)
+          for (int v = li; v < nwg; v += 16) s += ld_coh(&part[v * PNB + j]);
+        s = sum16(s);
+        if (li == 0 && j >= cc && j < pw) sg[j] = s;
+        if (tid < pw) srow[tid] = ld_coh(&bcast[tid]);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const double alpha = srow[cc], xn2 = sg[cc];
+        double beta, tau, scale;
+        if (xn2 == 0.0) {
+          beta = alpha;
+          tau = 0.0;
+          scale = 0.0;
+        } else {
+          const double nrm = sqrt(alpha * alpha + xn2);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        shh[0] = beta;
+        shh[1] = tau;
+        shh[2] = scale;
+        stau[c] = tau;
+        if (w == 0) a.tau[c] = tau;
+      }
+      __syncthreads();
+      if (tid < pw && tid > cc) sw[tid] = shh[1] * (srow[tid] + shh[2] * sg[tid]);
+      __syncthreads();
+      {
+        const double beta = shh[0], scale = shh[2];
+        double* xw = S + c * ldS;
+        for (int rl = tid; rl < nrows; rl += 256) {
+          const int r = rb + rl;
+          if (r > c) {
+            const double v = xw[rl] * scale;
+            for (int jj = cc + 1; jj < pw; ++jj) S[(c0 + jj) * ldS + rl] -= v * sw[jj];
+            xw[rl] = v;
+          } else if (r == c) {
+            for (int jj = cc + 1; jj < pw; ++jj) S[(c0 + jj) * ldS + rl] -= sw[jj];
+            xw[rl] = beta;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    auto vs = [&](int rl, int t) -> double {
+      const int r = rb + rl, d = c0 + t;
+      return r > d ? S[d * ldS + rl] : (r == d ? 1.0 : 0.0);
+    };
+    const int rl0 = max(0, c0 - rb);
+    // Partial products Vs^T [V_prev | Vs | P_rest] over my rows.
+    for (int j = tid; j < nb; j += 256) {
+      double acc[PNB];
+#pragma unroll
+      for (int t = 0; t < PNB; ++t) acc[t] = 0.0;
+      for (int rl = rl0; rl < nrows; ++rl) {
+        const double rop = (j >= c0 && j < c0 + pw) ? vs(rl, j - c0) : S[j * ldS + rl];
+#pragma unroll
+        for (int t = 0; t < PNB; ++t)
+          if (t < pw) acc[t] += vs(rl, t) * rop;
+      }
+#pragma unroll
+      for (int t = 0; t < PNB; ++t)
+        if (t < pw) st_coh(&a.bpart[((int64_t)w * PNB + t) * nb + j], acc[t]);
+    }
+    grid_sync_lean(a.bar, nwg, a.err);
+    {
+      const int E = pw * nb;
+      const int e0 = (int)((int64_t)w * E / nwg), e1 = (int)((int64_t)(w + 1) * E / nwg);
+      for (int e = e0 + tid; e < e1; e += 256) {
+        const int t = e / nb, j = e % nb;
+        double s = 0.0;
+        for (int v = 0; v < nwg; ++v) s += ld_coh(&a.bpart[((int64_t)v * PNB + t) * nb + j]);
+        st_coh(&a.red[e], s);
+      }
+    }
+    grid_sync_lean(a.bar, nwg, a.err);
+    for (int e = tid; e < pw * nb; e += 256) sred[e] = ld_coh(&a.red[e]);
+    __syncthreads();
+    for (int t = 0; t < pw; ++t) {
+      if (tid < t) {
+        double s = 0.0;
+        for (int k = tid; k < t; ++k) s += sTs[tid * PNB + k] * sred[k * nb + c0 + t];
+        sTs[tid * PNB + t] = -stau[c0 + t] * s;
+      } else if (tid < PNB) {
+        sTs[tid * PNB + t] = tid == t ? stau[c0 + t] : 0.0;
+      }
+      __syncthreads();
+    }
+    // Z(k,t) = sum_tp (V_prev^T Vs)(k,tp) Ts(tp,t), in place over sred[., k<c0].
+    for (int k = tid; k < c0; k += 256) {
+      double mk[PNB];
+#pragma unroll
+      for (int t = 0; t < PNB; ++t) mk[t] = t < pw ? sred[t * nb + k] : 0.0;
+#pragma unroll
+      for (int t = 0; t < PNB; ++t) {
+        if (t >= pw) continue;
+        double z = 0.0;
+        for (int tp = 0; tp <= t; ++tp) z += mk[tp] * sTs[tp * PNB + t];
+        sred[t * nb + k] = z;
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      for (int e = tid; e < pw * pw; e += 256) {
+        const int i = e / pw, t = e % pw;
+        st_coh(&a.Tw[(c0 + i) + (int64_t)(c0 + t) * a.ldtw], sTs[i * PNB + t]);
+      }
+      for (int e = tid; e < pw * c0; e += 256) {
+        const int i = e % pw, j = e / pw;
+        st_coh(&a.Tw[(c0 + i) + (int64_t)j * a.ldtw], 0.0);
+      }
+    }
+    // Tw(i, c0+t) = -sum_{k=i}^{c0-1} Tw(i,k) Z(k,t), rows i = w, w+nwg, ...
+    for (int i = w; i < c0; i += nwg) {
+      for (int k = i + tid; k < c0; k += 256) srowTw[k] = ld_coh(&a.Tw[i + (int64_t)k * a.ldtw]);
+      __syncthreads();
+      if (tid < pw) {
+        double s = 0.0;
+        for (int k = i; k < c0; ++k) s += srowTw[k] * sred[tid * nb + k];
+        st_coh(&a.Tw[i + (int64_t)(c0 + tid) * a.ldtw], -s);
+      }
+      __syncthreads();
+    }
+    // P_rest -= Vs (Ts^T W) on my rows, in LDS.
+    for (int j = c0 + pw + tid; j < nb; j += 256) {
+      double wp[PNB];
+#pragma unroll
+      for (int t = 0; t < PNB; ++t) {
+        double s = 0.0;
+        if (t < pw)
+          for (int tp = 0; tp <= t; ++tp) s += sTs[tp * PNB + t] * sred[tp * nb + j];
+        wp[t] = s;
+      }
+      double* pj = S + j * ldS;
+      for (int rl = rl0; rl < nrows; ++rl) {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < PNB; ++t)
+          if (t < pw) s += vs(rl, t) * wp[t];
+        pj[rl] -= s;
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < nb * nrows; idx += 256) {
+    const int j = idx / nrows, rl = idx % nrows;
+    a.P[rb + rl + (int64_t)j * ldp] = S[j * ldS + rl];
+  }
+}
+
 __global__ void k_init_sync(unsigned* bar) {
   if (threadIdx.x == 0) {
     bar[0] = 0u;
@@ -340,8 +599,47 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
                     double* Tw, int64_t ldtw, const PanelWork& w) {
   if (nb <= 0) return hipSuccess;
   if (nb > MAXB || Mp < nb) return hipErrorInvalidValue;
+  static int cu_count = 0;
+  static int kLdsBytes = 0;
+  static bool attr_set = false;
+  if (!cu_count) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cu_count = 1;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      lds = 64 * 1024;
+    kLdsBytes = std::min(lds, 160 * 1024);
+    if (hipFuncSetAttribute((const void*)k_panel_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsBytes) == hipSuccess)
+      attr_set = true;
+    (void)hipGetLastError();
+  }
+  // LDS-resident variant: slab of `chunk` rows x nb columns per workgroup.
+  const int fixed = kFixedLdsDoubles(nb);
+  const int max_ld = (kLdsBytes / 8 - fixed) / nb;
+  const int chunk_max = std::min(kPanelMaxRows, max_ld - 1);
+  if (attr_set && chunk_max >= 1) {
+    int nwg = (Mp + chunk_max - 1) / chunk_max;
+    if (nwg <= std::min(cu_count, kPanelMaxWG)) {
+      const int chunk = (Mp + nwg - 1) / nwg;
+      nwg = (Mp + chunk - 1) / chunk;
+      const int ldS = chunk | 1;
+      const size_t shmem = ((size_t)nb * ldS + fixed) * sizeof(double);
+      hipLaunchKernelGGL(k_init_sync, dim3(1), dim3(64), 0, st, w.bar);
+      PanelArgs2 a{Mp, nb, nwg, chunk, ldS, P, ldp, tau, Tw, ldtw, w.part, w.bcast, w.bpart,
+                   w.red, w.bar, w.err};
+      void* args[] = {&a};
+      const int slot = prof_mark(st);
+      hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel_lds, dim3(nwg), dim3(256),
+                                                args, (unsigned)shmem, st);
+      prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb);
+      return e;
+    }
+  }
+  // Global-memory variant for slabs that do not fit in LDS.
   int nwg = (Mp + 63) / 64;
-  nwg = max(1, min(nwg, kPanelMaxWG));
+  nwg = std::max(1, std::min(nwg, kPanelMaxWGGlobal));
   int chunk = (Mp + nwg - 1) / nwg;
   if (chunk > kPanelMaxRows) return hipErrorInvalidValue;
   nwg = (Mp + chunk - 1) / chunk;

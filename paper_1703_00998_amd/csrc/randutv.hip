@@ -29,8 +29,8 @@ using namespace rutv;
 namespace {
 
 constexpr int kMaxB = 256;
-constexpr int kMaxPanelRows = kPanelMaxWG * kPanelMaxRows;
-constexpr int kJacobiSweeps = 60;
+constexpr int kMaxPanelRows = kPanelMaxWGGlobal * kPanelMaxRows;
+constexpr int kJacobiSweeps = 40;
 
 struct Layout {
   size_t Y, Vh, Z, P, Uh, W, W2, C, C2, TwV, TwU, tauV, tauU, Rst, Ust, Vst, D, Jw, Jv, Ftmp,
@@ -78,7 +78,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
   L.split_elems = (size_t)kMaxSplitK * std::max(mb, nb);
   L.split = take(L.split_elems * d);
   L.nrm = take(1040 * d);
-  L.ints = take((2 * s + 8) * sizeof(int));
+  L.ints = take((2 * s + s * kJacobiSweeps + 8) * sizeof(int));
   L.panel = take(panel_work_bytes((int)b));
   L.total = off;
   return L;
@@ -367,7 +367,8 @@ int randutv_panel_qr(int64_t Mp, int64_t nb, double* P, int64_t ldp, double* tau
 
 size_t randutv_small_svd_work_size(int64_t count, int64_t ld) {
   if (count < 1 || ld < 1 || ld > 1024) return 0;
-  return al256((size_t)2 * count * ld * ld * sizeof(double)) + al256(2 * count * sizeof(int));
+  return al256((size_t)2 * count * ld * ld * sizeof(double)) +
+         al256((size_t)(2 + kJacobiSweeps) * count * sizeof(int));
 }
 
 int randutv_small_svd(int64_t count, const int* nbs, int64_t ld, const double* R, double* Us,
