@@ -50,6 +50,8 @@ struct PanelWork {
   double* bcast;  // 2 * kPanelNB                (pivot row broadcast)
   double* bpart;  // kPanelMaxWG * kPanelNB * bmax (block-update partials)
   double* red;    // kPanelNB * bmax            (reduced block products)
+  double* gram;   // 2 * kPanelMaxWG * 256      (sub-panel Gram partials)
+  double* qtop;   // kPanelNB^2                 (top rows of the sub-panel Q)
   unsigned* bar;  // 2 counters                  (grid barrier)
   int* err;       // 1 flag                      (barrier spin limit hit)
 };

@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
 // write-back and the small cross-slab reduction partials, which are written
 // and read with device-coherent (agent-scope) accesses.
 struct PanelArgs2 {
-  int Mp, nb, nwg, chunk, ldS;
+  int Mp, nb, nwg, chunk, ldS, use_hr;
   double* P;
   int64_t ldp;
   double* tau;
@@ -314,6 +314,8 @@ struct PanelArgs2 {
   double* red;
   unsigned* bar;
   int* err;
+  double* gram;  // 2 * kPanelMaxWG * 256 Gram partials
+  double* qtop;  // kPanelNB^2 published top rows of Q
 };
 
 __device__ inline void st_coh(double* p, double v) {
@@ -323,17 +325,24 @@ __device__ inline double ld_coh(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier whose agent-scope release/acquire fences are issued by one
-// wave only (the workgroup barriers order the other waves around it).
-__device__ void grid_sync_lean(unsigned* bar, unsigned nwg, int* err) {
+// Grid barrier for the LDS-resident kernel.  All data exchanged across
+// workgroups in that kernel is written and read with device-coherent
+// (agent-scope atomic, sc1) accesses, so no L2 writeback or invalidation is
+// needed: each wave waits until its own coherent stores are acknowledged
+// (vmcnt = 0) before the workgroup arrives, and data is read only after the
+// generation change is observed.
+__device__ inline void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+__device__ void grid_sync_coh(unsigned* bar, unsigned nwg, int* err) {
+  wait_stores();
   __syncthreads();
   if (threadIdx.x == 0 && nwg > 1) {
-    fence_release();
     const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (a == nwg - 1) {
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      wait_stores();
+      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned it = 0;
       while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
@@ -345,16 +354,249 @@ __device__ void grid_sync_lean(unsigned* bar, unsigned nwg, int* err) {
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    fence_acquire();
   }
   __syncthreads();
 }
 
-constexpr int kFixedLdsDoubles(int nb) { return PNB * nb + PNB * PNB + 2 * nb + 3 * PNB + 8; }
+// LDS besides the slab: sred, sTs, stau, srowTw, sg/srow/sw/shh, the
+// sub-panel copy (PNB columns of the slab stride, counted in the slab) and
+// six PNB x PNB matrices + signs + flags of the CholeskyQR2 path.
+constexpr int kFixedLdsDoubles(int nb) {
+  return PNB * nb + PNB * PNB + 2 * nb + 3 * PNB + 8 + 6 * PNB * PNB + PNB + 8;
+}
+
+
+// ---- CholeskyQR2 + Householder reconstruction of one sub-panel ----------
+__device__ inline v4d mfma64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Order LDS accesses among the lanes of one wave (no workgroup barrier).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The Gram matrix X^T X of the sub-panel's active rows (>= c0), summed over
+// all workgroups in a fixed order.  One grid barrier.  Result in sG (full).
+__device__ void gram_reduce(const double* S, int c0, int ldS, int rl0, int nrows, int pw,
+                            double* gpart, int w, int nwg, double* sG, unsigned* bar, int* err) {
+  const int tid = threadIdx.x;
+  const int i = tid >> 4, j = tid & 15;
+  const bool act = i < pw && j < pw && i <= j;
+  double s = 0.0;
+  if (act) {
+    const double* xi = S + (c0 + i) * ldS;
+    const double* xj = S + (c0 + j) * ldS;
+    for (int rl = rl0; rl < nrows; ++rl) s += xi[rl] * xj[rl];
+  }
+  st_coh(&gpart[w * 256 + tid], s);
+  grid_sync_coh(bar, nwg, err);
+  double tot = 0.0;
+  if (act) {
+    for (int v0 = 0; v0 < nwg; v0 += 32) {
+      double vals[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) vals[k] = v0 + k < nwg ? ld_coh(&gpart[(v0 + k) * 256 + tid]) : 0.0;
+#pragma unroll
+      for (int k = 0; k < 32; ++k) tot += vals[k];
+    }
+    sG[i * PNB + j] = tot;
+    sG[j * PNB + i] = tot;
+  }
+  __syncthreads();
+}
+
+// Upper Cholesky factor R (R^T R = G), pw x pw, computed by one wave.
+// Returns false when a pivot falls below rel * max diag(G) (same value in
+// every lane).
+__device__ bool chol_wave(const double* sG, double* sR, int pw, double rel) {
+  const int lane = threadIdx.x & 63;
+  double gmax = 0.0;
+  for (int k = 0; k < pw; ++k) gmax = fmax(gmax, sG[k * PNB + k]);
+  const double thr = rel * gmax;
+  bool ok = true;
+  for (int k = 0; k < pw; ++k) {
+    double d = sG[k * PNB + k];
+    for (int m = 0; m < k; ++m) d -= sR[m * PNB + k] * sR[m * PNB + k];
+    ok = ok && (d > thr);
+    const double rkk = sqrt(d > thr ? d : 1.0);
+    if (lane < pw) {
+      double v = 0.0;
+      if (lane > k) {
+        v = sG[k * PNB + lane];
+        for (int m = 0; m < k; ++m) v -= sR[m * PNB + k] * sR[m * PNB + lane];
+        v /= rkk;
+      } else if (lane == k) {
+        v = rkk;
+      }
+      sR[k * PNB + lane] = v;
+    }
+    wave_sync();
+  }
+  return ok;
+}
+
+// In place X <- X R^{-1} on rows [r0, r1) of the sub-panel columns (one
+// thread per row; R upper triangular pw x pw).
+__device__ void rsolve_rows(double* S, int c0, int ldS, int r0, int r1, int pw, const double* sR) {
+  for (int rl = r0 + threadIdx.x; rl < r1; rl += blockDim.x) {
+    double x[PNB];
+#pragma unroll
+    for (int jc = 0; jc < PNB; ++jc) {
+      if (jc >= pw) break;
+      double v = S[(c0 + jc) * ldS + rl];
+      for (int i = 0; i < jc; ++i) v -= x[i] * sR[i * PNB + jc];
+      x[jc] = v / sR[jc * PNB + jc];
+    }
+#pragma unroll
+    for (int jc = 0; jc < PNB; ++jc) {
+      if (jc >= pw) break;
+      S[(c0 + jc) * ldS + rl] = x[jc];
+    }
+  }
+}
+
+struct HrBufs {
+  double *sP0, *sG, *sR1, *sR2, *sQt, *sLU, *ssgn;
+  int* sflag;
+};
+
+// Factor the sub-panel columns c0..c0+pw-1 (active rows >= c0) by
+// CholeskyQR2, then rebuild its Householder vectors, tau and R from Q by the
+// LU of Q - S (S = diag(s), s_k = -sign of the running pivot, which is the
+// dlarfg choice), so the result matches column-by-column Householder QR in
+// exact arithmetic.  Two grid barriers; the 16 x 16 factorizations run in
+// wave 0.  Returns false, with the sub-panel untouched, when the sub-panel is
+// too ill-conditioned for CholeskyQR2 or a column has an exactly zero tail
+// (dlarfg's tau = 0 case).
+__device__ bool subpanel_cholqr_hr(double* S, int c0, int pw, int ldS, int rb, int nrows,
+                                   int w, int nwg, const PanelArgs2& a, const HrBufs& hb,
+                                   double* stau) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rl0 = max(0, c0 - rb);
+  for (int idx = tid; idx < pw * nrows; idx += 256) {
+    const int i = idx / nrows, rl = idx % nrows;
+    hb.sP0[i * ldS + rl] = S[(c0 + i) * ldS + rl];
+  }
+  gram_reduce(S, c0, ldS, rl0, nrows, pw, a.gram, w, nwg, hb.sG, a.bar, a.err);
+  if (wave == 0) {
+    const bool ok1 = chol_wave(hb.sG, hb.sR1, pw, 1e-13);
+    if (lane == 0) hb.sflag[0] = ok1;
+  }
+  __syncthreads();
+  if (!hb.sflag[0]) return false;
+  rsolve_rows(S, c0, ldS, rl0, nrows, pw, hb.sR1);
+  __syncthreads();
+  // Publish Q1's rows c0..c0+pw-1 (those I own).
+  for (int idx = tid; idx < pw * pw; idx += 256) {
+    const int rho = idx / pw, i = idx % pw;
+    const int r = c0 + rho;
+    if (r >= rb && r < rb + nrows) st_coh(&a.qtop[rho * PNB + i], S[(c0 + i) * ldS + (r - rb)]);
+  }
+  gram_reduce(S, c0, ldS, rl0, nrows, pw, a.gram + kPanelMaxWG * 256, w, nwg, hb.sG, a.bar,
+              a.err);
+  for (int idx = tid; idx < pw * pw; idx += 256) {
+    const int rho = idx / pw, i = idx % pw;
+    hb.sQt[rho * PNB + i] = ld_coh(&a.qtop[rho * PNB + i]);
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // ||Q1^T Q1 - I||_max < 0.1, else CholeskyQR lost too much orthogonality.
+    bool ok = true;
+    for (int e = lane; e < pw * pw; e += 64) {
+      const int i = e / pw, j = e % pw;
+      ok = ok && fabs(hb.sG[i * PNB + j] - (i == j ? 1.0 : 0.0)) < 0.1;
+    }
+    ok = __all(ok);
+    ok = chol_wave(hb.sG, hb.sR2, pw, 1e-3) && ok;
+    // Qt <- Qt R2^{-1}; R <- R2 R1 (into sLU, then back to sR1).
+    if (lane < pw) {
+      double x[PNB];
+#pragma unroll
+      for (int jc = 0; jc < PNB; ++jc) {
+        if (jc >= pw) break;
+        double v = hb.sQt[lane * PNB + jc];
+        for (int i = 0; i < jc; ++i) v -= x[i] * hb.sR2[i * PNB + jc];
+        x[jc] = v / hb.sR2[jc * PNB + jc];
+      }
+#pragma unroll
+      for (int jc = 0; jc < PNB; ++jc) {
+        if (jc >= pw) break;
+        hb.sQt[lane * PNB + jc] = x[jc];
+      }
+    }
+    for (int e = lane; e < pw * pw; e += 64) {
+      const int i = e / pw, jc = e % pw;
+      double v = 0.0;
+      for (int k = i; k <= jc; ++k) v += hb.sR2[i * PNB + k] * hb.sR1[k * PNB + jc];
+      hb.sLU[i * PNB + jc] = i <= jc ? v : 0.0;
+    }
+    wave_sync();
+    for (int e = lane; e < pw * pw; e += 64) {
+      const int i = e / pw, jc = e % pw;
+      hb.sR1[i * PNB + jc] = hb.sLU[i * PNB + jc];
+      hb.sLU[i * PNB + jc] = hb.sQt[i * PNB + jc];
+    }
+    wave_sync();
+    // LU of Qt - diag(s) without pivoting; s_k = -sign(running pivot).
+    double* A = hb.sLU;
+    for (int k = 0; k < pw; ++k) {
+      const double d = A[k * PNB + k];
+      ok = ok && fabs(d) < 1.0 - 1.0 / 1125899906842624.0;  // else a zero tail
+      const double sk = d >= 0.0 ? -1.0 : 1.0;
+      const double piv = d - sk;
+      wave_sync();
+      if (lane == 0) {
+        hb.ssgn[k] = sk;
+        A[k * PNB + k] = piv;
+      }
+      if (lane > k && lane < pw) A[lane * PNB + k] /= piv;
+      wave_sync();
+      for (int e = lane; e < pw * pw; e += 64) {
+        const int r = e / pw, cc = e % pw;
+        if (r > k && cc > k) A[r * PNB + cc] -= A[r * PNB + k] * A[k * PNB + cc];
+      }
+      wave_sync();
+    }
+    if (lane == 0) hb.sflag[1] = ok;
+  }
+  __syncthreads();
+  if (!hb.sflag[1]) {
+    for (int idx = tid; idx < pw * nrows; idx += 256) {
+      const int i = idx / nrows, rl = idx % nrows;
+      S[(c0 + i) * ldS + rl] = hb.sP0[i * ldS + rl];
+    }
+    __syncthreads();
+    return false;
+  }
+  // Second CholeskyQR pass on my rows: Q = Q1 R2^{-1}.
+  rsolve_rows(S, c0, ldS, rl0, nrows, pw, hb.sR2);
+  __syncthreads();
+  // Rows below the sub-panel's top: V = Q U^{-1} (U = upper part of the LU).
+  const int rtop = max(rl0, min(nrows, c0 + pw - rb));
+  rsolve_rows(S, c0, ldS, rtop, nrows, pw, hb.sLU);
+  // Top rows c0..c0+pw-1 that I own: R (signs applied) on/above, L below.
+  for (int idx = tid; idx < pw * pw; idx += 256) {
+    const int rho = idx / pw, i = idx % pw;
+    const int r = c0 + rho;
+    if (r >= rb && r < rb + nrows)
+      S[(c0 + i) * ldS + (r - rb)] =
+          rho <= i ? hb.ssgn[rho] * hb.sR1[rho * PNB + i] : hb.sLU[rho * PNB + i];
+  }
+  if (tid < pw) {
+    const double tau = -hb.sLU[tid * PNB + tid] * hb.ssgn[tid];
+    stau[c0 + tid] = tau;
+    if (w == 0) a.tau[c0 + tid] = tau;
+  }
+  __syncthreads();
+  return true;
+}
 
 __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
   extern __shared__ double smem[];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int w = blockIdx.x;
   const int nwg = a.nwg, nb = a.nb, Mp = a.Mp, ldS = a.ldS;
   const int rb = w * a.chunk;
@@ -369,6 +611,16 @@ __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
   double* srow = sg + PNB;
   double* sw = srow + PNB;
   double* shh = sw + PNB;
+  HrBufs hb;
+  hb.sG = shh + 8;
+  hb.sR1 = hb.sG + PNB * PNB;
+  hb.sR2 = hb.sR1 + PNB * PNB;
+  hb.sQt = hb.sR2 + PNB * PNB;
+  hb.sLU = hb.sQt + PNB * PNB;
+  hb.ssgn = hb.sLU + PNB * PNB;
+  hb.sflag = (int*)(hb.ssgn + PNB);
+  hb.sP0 = hb.ssgn + PNB + 8;  // PNB columns of stride ldS
+  double* sVd = hb.sP0;        // dense sub-panel reflectors once factored
   const int64_t ldp = a.ldp;
 
   for (int idx = tid; idx < nb * nrows; idx += 256) {
@@ -379,7 +631,9 @@ __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
   int colstep = 0;
   for (int c0 = 0; c0 < nb; c0 += PNB) {
     const int pw = min(PNB, nb - c0);
-    for (int cc = 0; cc < pw; ++cc, ++colstep) {
+    const bool hr_done =
+        a.use_hr && pw > 1 && subpanel_cholqr_hr(S, c0, pw, ldS, rb, nrows, w, nwg, a, hb, stau);
+    for (int cc = 0; cc < pw && !hr_done; ++cc, ++colstep) {
       const int c = c0 + cc;
       const int buf = colstep & 1;
       double* part = a.part + buf * (kPanelMaxWG * PNB);
@@ -397,12 +651,20 @@ __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
         if (li == 0 && j >= cc && j < pw) st_coh(&part[w * PNB + j], s);
         if (c >= rb && c < re && tid < pw) st_coh(&bcast[tid], S[(c0 + tid) * ldS + (c - rb)]);
       }
-      grid_sync_lean(a.bar, nwg, a.err);
+      grid_sync_coh(a.bar, nwg, a.err);
       {
         const int j = tid >> 4, li = tid & 15;
         double s = 0.0;
-        if (j >= cc && j < pw)
-          for (int v = li; v < nwg; v += 16) s += ld_coh(&part[v * PNB + j]);
+        if (j >= cc && j < pw) {
+          double vals[kPanelMaxWG / 16];
+#pragma unroll
+          for (int k = 0; k < kPanelMaxWG / 16; ++k) {
+            const int v = li + 16 * k;
+            vals[k] = v < nwg ? ld_coh(&part[v * PNB + j]) : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < kPanelMaxWG / 16; ++k) s += vals[k];
+        }
         s = sum16(s);
         if (li == 0 && j >= cc && j < pw) sg[j] = s;
         if (tid < pw) srow[tid] = ld_coh(&bcast[tid]);
@@ -447,50 +709,103 @@ __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
       }
       __syncthreads();
     }
-    auto vs = [&](int rl, int t) -> double {
-      const int r = rb + rl, d = c0 + t;
-      return r > d ? S[d * ldS + rl] : (r == d ? 1.0 : 0.0);
-    };
     const int rl0 = max(0, c0 - rb);
-    // Partial products Vs^T [V_prev | Vs | P_rest] over my rows.
-    for (int j = tid; j < nb; j += 256) {
-      double acc[PNB];
-#pragma unroll
-      for (int t = 0; t < PNB; ++t) acc[t] = 0.0;
-      for (int rl = rl0; rl < nrows; ++rl) {
-        const double rop = (j >= c0 && j < c0 + pw) ? vs(rl, j - c0) : S[j * ldS + rl];
-#pragma unroll
-        for (int t = 0; t < PNB; ++t)
-          if (t < pw) acc[t] += vs(rl, t) * rop;
+    // Dense reflectors of the sub-panel on my rows: Vd(t, rl), zero above
+    // the diagonal and for t >= pw, one on it.
+    for (int idx = tid; idx < PNB * nrows; idx += 256) {
+      const int t = idx / nrows, rl = idx % nrows;
+      const int r = rb + rl, d = c0 + t;
+      sVd[t * ldS + rl] = t < pw ? (r > d ? S[d * ldS + rl] : (r == d ? 1.0 : 0.0)) : 0.0;
+    }
+    __syncthreads();
+    // Partial products Vs^T [V_prev | Vs | P_rest] (kPanelNB x nb) over my
+    // rows on FP64 MFMA: A = Vd^T (t x rows), B = the slab (rows x columns),
+    // the sub-panel's own columns taken from Vd.  Output D(t, j) sits in
+    // register r of lane l at t = l/16 + 4r, j = j0 + l%16.
+    for (int jb = wave; jb < (nb + 15) / 16; jb += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      const int j = jb * 16 + (lane & 15);
+      const bool jin = j < nb;
+      const bool jv = j >= c0 && j < c0 + pw;
+      for (int k0 = rl0; k0 < nrows; k0 += 4) {
+        const int rl = k0 + (lane >> 4);
+        const bool rin = rl < nrows;
+        const double av = rin ? sVd[(lane & 15) * ldS + rl] : 0.0;
+        const double bv = (rin && jin) ? (jv ? sVd[(j - c0) * ldS + rl] : S[j * ldS + rl]) : 0.0;
+        acc = mfma64(av, bv, acc);
       }
 #pragma unroll
-      for (int t = 0; t < PNB; ++t)
-        if (t < pw) st_coh(&a.bpart[((int64_t)w * PNB + t) * nb + j], acc[t]);
+      for (int r = 0; r < 4; ++r) {
+        const int t = (lane >> 4) + 4 * r;
+        if (t < pw && jin) st_coh(&a.bpart[((int64_t)w * PNB + t) * nb + j], acc[r]);
+      }
     }
-    grid_sync_lean(a.bar, nwg, a.err);
+    grid_sync_coh(a.bar, nwg, a.err);
     {
+      // Entries [e0, e1) of the kPanelNB x nb product are summed here over
+      // the nwg partials: 8 threads per entry, each over every 8th partial
+      // with independent loads in flight, then a fixed-order 8-lane sum.
       const int E = pw * nb;
       const int e0 = (int)((int64_t)w * E / nwg), e1 = (int)((int64_t)(w + 1) * E / nwg);
-      for (int e = e0 + tid; e < e1; e += 256) {
-        const int t = e / nb, j = e % nb;
+      const int sub = tid & 7;
+      for (int eb = e0; eb < e1; eb += 32) {
+        const int e = eb + (tid >> 3);
         double s = 0.0;
-        for (int v = 0; v < nwg; ++v) s += ld_coh(&a.bpart[((int64_t)v * PNB + t) * nb + j]);
-        st_coh(&a.red[e], s);
+        if (e < e1) {
+          const int t = e / nb, j = e % nb;
+          double vals[kPanelMaxWG / 8];
+#pragma unroll
+          for (int k = 0; k < kPanelMaxWG / 8; ++k) {
+            const int v = sub + 8 * k;
+            vals[k] = v < nwg ? ld_coh(&a.bpart[((int64_t)v * PNB + t) * nb + j]) : 0.0;
+          }
+#pragma unroll
+          for (int k = 0; k < kPanelMaxWG / 8; ++k) s += vals[k];
+        }
+        s += __shfl_xor(s, 4, 8);
+        s += __shfl_xor(s, 2, 8);
+        s += __shfl_xor(s, 1, 8);
+        if (e < e1 && sub == 0) st_coh(&a.red[e], s);
       }
     }
-    grid_sync_lean(a.bar, nwg, a.err);
-    for (int e = tid; e < pw * nb; e += 256) sred[e] = ld_coh(&a.red[e]);
+    grid_sync_coh(a.bar, nwg, a.err);
+    {
+      const int E = pw * nb;
+      for (int e0 = 0; e0 < E; e0 += 256 * 8) {
+        double vals[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int e = e0 + tid + 256 * k;
+          vals[k] = e < E ? ld_coh(&a.red[e]) : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int e = e0 + tid + 256 * k;
+          if (e < E) sred[e] = vals[k];
+        }
+      }
+    }
     __syncthreads();
-    for (int t = 0; t < pw; ++t) {
-      if (tid < t) {
-        double s = 0.0;
-        for (int k = tid; k < t; ++k) s += sTs[tid * PNB + k] * sred[k * nb + c0 + t];
-        sTs[tid * PNB + t] = -stau[c0 + t] * s;
-      } else if (tid < PNB) {
-        sTs[tid * PNB + t] = tid == t ? stau[c0 + t] : 0.0;
+    // Ts: compact-WY factor of the sub-panel, column recurrence
+    // Ts(0:t,t) = -tau_t Ts(0:t,0:t) Gram(0:t,t), Ts(t,t) = tau_t (wave 0).
+    if (wave == 0) {
+      for (int t = 0; t < PNB; ++t) {
+        if (lane < PNB) {
+          double v = 0.0;
+          if (t < pw) {
+            if (lane < t) {
+              for (int k = lane; k < t; ++k) v += sTs[lane * PNB + k] * sred[k * nb + c0 + t];
+              v = -stau[c0 + t] * v;
+            } else if (lane == t) {
+              v = stau[c0 + t];
+            }
+          }
+          sTs[lane * PNB + t] = v;
+        }
+        wave_sync();
       }
-      __syncthreads();
     }
+    __syncthreads();
     // Z(k,t) = sum_tp (V_prev^T Vs)(k,tp) Ts(tp,t), in place over sred[., k<c0].
     for (int k = tid; k < c0; k += 256) {
       double mk[PNB];
@@ -502,6 +817,19 @@ __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
         double z = 0.0;
         for (int tp = 0; tp <= t; ++tp) z += mk[tp] * sTs[tp * PNB + t];
         sred[t * nb + k] = z;
+      }
+    }
+    // W' = Ts^T W in place over sred[., j >= c0+pw].
+    for (int j = c0 + pw + tid; j < nb; j += 256) {
+      double wj[PNB];
+#pragma unroll
+      for (int t = 0; t < PNB; ++t) wj[t] = t < pw ? sred[t * nb + j] : 0.0;
+#pragma unroll
+      for (int t = 0; t < PNB; ++t) {
+        if (t >= pw) continue;
+        double v = 0.0;
+        for (int tp = 0; tp <= t; ++tp) v += sTs[tp * PNB + t] * wj[tp];
+        sred[t * nb + j] = v;
       }
     }
     __syncthreads();
@@ -526,23 +854,28 @@ __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
       }
       __syncthreads();
     }
-    // P_rest -= Vs (Ts^T W) on my rows, in LDS.
-    for (int j = c0 + pw + tid; j < nb; j += 256) {
-      double wp[PNB];
+    // P_rest -= Vd W' on my rows, FP64 MFMA over 16 x 16 tiles:
+    // A(row, t) = Vd(t, row), B(t, j) = W'(t, j), K = kPanelNB.
+    {
+      const int jr0 = c0 + pw;
+      const int ncb = (nb - jr0 + 15) / 16, nrb = (nrows - rl0 + 15) / 16;
+      for (int tile = wave; tile < ncb * nrb; tile += 4) {
+        const int rt = tile % nrb, ct = tile / nrb;
+        const int r0 = rl0 + rt * 16, j0 = jr0 + ct * 16;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int t = 0; t < PNB; ++t) {
-        double s = 0.0;
-        if (t < pw)
-          for (int tp = 0; tp <= t; ++tp) s += sTs[tp * PNB + t] * sred[tp * nb + j];
-        wp[t] = s;
-      }
-      double* pj = S + j * ldS;
-      for (int rl = rl0; rl < nrows; ++rl) {
-        double s = 0.0;
+        for (int t0 = 0; t0 < PNB; t0 += 4) {
+          const int rl = r0 + (lane & 15), t = t0 + (lane >> 4);
+          const int j = j0 + (lane & 15);
+          const double av = (rl < nrows && t < pw) ? sVd[t * ldS + rl] : 0.0;
+          const double bv = (j < nb && t < pw) ? sred[t * nb + j] : 0.0;
+          acc = mfma64(av, bv, acc);
+        }
 #pragma unroll
-        for (int t = 0; t < PNB; ++t)
-          if (t < pw) s += vs(rl, t) * wp[t];
-        pj[rl] -= s;
+        for (int r = 0; r < 4; ++r) {
+          const int rl = r0 + (lane >> 4) + 4 * r, j = j0 + (lane & 15);
+          if (rl < nrows && j < nb) S[j * ldS + rl] -= acc[r];
+        }
       }
     }
     __syncthreads();
@@ -577,7 +910,8 @@ __global__ void k_extract(int Mp, int nb, const double* __restrict__ P, int64_t 
 }  // namespace
 
 size_t panel_work_bytes(int bmax) {
-  size_t d = 2 * kPanelMaxWG * PNB + 2 * PNB + (size_t)kPanelMaxWG * PNB * bmax + PNB * bmax;
+  size_t d = 2 * kPanelMaxWG * PNB + 2 * PNB + (size_t)kPanelMaxWG * PNB * bmax + PNB * bmax +
+             2 * kPanelMaxWG * 256 + PNB * PNB;
   return d * sizeof(double) + 256;
 }
 
@@ -591,6 +925,10 @@ void panel_work_carve(void* base, int bmax, PanelWork* w) {
   p += (size_t)kPanelMaxWG * PNB * bmax;
   w->red = p;
   p += PNB * bmax;
+  w->gram = p;
+  p += 2 * kPanelMaxWG * 256;
+  w->qtop = p;
+  p += PNB * PNB;
   w->bar = (unsigned*)p;
   w->err = (int*)(w->bar + 2);
 }
@@ -617,7 +955,7 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
   }
   // LDS-resident variant: slab of `chunk` rows x nb columns per workgroup.
   const int fixed = kFixedLdsDoubles(nb);
-  const int max_ld = (kLdsBytes / 8 - fixed) / nb;
+  const int max_ld = (kLdsBytes / 8 - fixed) / (nb + PNB);
   const int chunk_max = std::min(kPanelMaxRows, max_ld - 1);
   if (attr_set && chunk_max >= 1) {
     int nwg = (Mp + chunk_max - 1) / chunk_max;
@@ -625,10 +963,10 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
       const int chunk = (Mp + nwg - 1) / nwg;
       nwg = (Mp + chunk - 1) / chunk;
       const int ldS = chunk | 1;
-      const size_t shmem = ((size_t)nb * ldS + fixed) * sizeof(double);
+      const size_t shmem = ((size_t)(nb + PNB) * ldS + fixed) * sizeof(double);
       hipLaunchKernelGGL(k_init_sync, dim3(1), dim3(64), 0, st, w.bar);
-      PanelArgs2 a{Mp, nb, nwg, chunk, ldS, P, ldp, tau, Tw, ldtw, w.part, w.bcast, w.bpart,
-                   w.red, w.bar, w.err};
+      PanelArgs2 a{Mp, nb, nwg, chunk, ldS, nwg > 1 ? 1 : 0, P, ldp, tau, Tw, ldtw, w.part,
+                   w.bcast, w.bpart, w.red, w.bar, w.err, w.gram, w.qtop};
       void* args[] = {&a};
       const int slot = prof_mark(st);
       hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel_lds, dim3(nwg), dim3(256),
