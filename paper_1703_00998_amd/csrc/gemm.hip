@@ -21,18 +21,25 @@
 namespace rutv {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
+constexpr int BK = 16, PAD = 2;
 
 __device__ inline v4d mfma64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, int kper,
+// BM x BN output tile per 256-thread workgroup; 2 x 2 waves, each owning a
+// (BM/2) x (BN/2) quarter as (BM/32) x (BN/32) MFMA 16 x 16 blocks.  The
+// occupancy hint keeps registers low enough for two workgroups per CU, so
+// one workgroup's loads overlap the other's MFMAs (measured: 128 x 128 tiles
+// at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26 without the hint).
+template <bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256, 2) void k_dgemm(int M, int N, int K, int kper,
                                                const double* __restrict__ A, int64_t lda,
                                                const double* __restrict__ B, int64_t ldb,
                                                double* __restrict__ C, int64_t ldc,
                                                int64_t zstride, double alpha, double beta) {
+  constexpr int FM = BM / 32, FN = BN / 32;       // MFMA blocks per wave
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread
   __shared__ double As[2][BK][BM + PAD];
   __shared__ double Bs[2][BK][BN + PAD];
   const int tid = threadIdx.x;
@@ -43,41 +50,53 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, int kper,
   const int kend = min(K, kbeg + kper);
   if (gridDim.z > 1) C += (int64_t)blockIdx.z * zstride;
 
-  double ra[4], rb[4];
+  // Element r of this thread's share of the A (BM x BK) and B (BK x BN)
+  // slabs, chosen so that consecutive threads read consecutive addresses.
+  auto a_idx = [&](int r, int& i, int& k) {
+    if (!TA) { i = tid % BM; k = tid / BM + (256 / BM) * r; }
+    else     { k = tid % BK; i = tid / BK + (256 / BK) * r; }
+  };
+  auto b_idx = [&](int r, int& k, int& j) {
+    if (!TB) { k = tid % BK; j = tid / BK + (256 / BK) * r; }
+    else     { j = tid % BN; k = tid / BN + (256 / BN) * r; }
+  };
+  double ra[LA], rb[LB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LA; ++r) {
       int i, k;
-      if (!TA) { i = tid & 63; k = (tid >> 6) + 4 * r; }
-      else     { k = tid & 15; i = (tid >> 4) + 16 * r; }
+      a_idx(r, i, k);
       const int gi = m0 + i, gk = k0 + k;
       ra[r] = (gi < M && gk < kend) ? (TA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
-      int j;
-      if (!TB) { k = tid & 15; j = (tid >> 4) + 16 * r; }
-      else     { j = tid & 63; k = (tid >> 6) + 4 * r; }
-      const int gj = n0 + j, gk2 = k0 + k;
-      rb[r] = (gj < N && gk2 < kend) ? (TB ? B[gj + (int64_t)gk2 * ldb] : B[gk2 + (int64_t)gj * ldb]) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      int k, j;
+      b_idx(r, k, j);
+      const int gj = n0 + j, gk = k0 + k;
+      rb[r] = (gj < N && gk < kend) ? (TB ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb]) : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < LA; ++r) {
       int i, k;
-      if (!TA) { i = tid & 63; k = (tid >> 6) + 4 * r; }
-      else     { k = tid & 15; i = (tid >> 4) + 16 * r; }
+      a_idx(r, i, k);
       As[buf][k][i] = ra[r];
-      int j;
-      if (!TB) { k = tid & 15; j = (tid >> 4) + 16 * r; }
-      else     { j = tid & 63; k = (tid >> 6) + 4 * r; }
+    }
+#pragma unroll
+    for (int r = 0; r < LB; ++r) {
+      int k, j;
+      b_idx(r, k, j);
       Bs[buf][k][j] = rb[r];
     }
   };
 
-  v4d acc[2][2];
+  v4d acc[FM][FN];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < FM; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < FN; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
@@ -91,31 +110,32 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int K, int kper,
     if (t + 1 < nk) load(kbeg + (t + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      const double a0 = As[cur][kk + kr][wm * 32 + cr];
-      const double a1 = As[cur][kk + kr][wm * 32 + 16 + cr];
-      const double b0 = Bs[cur][kk + kr][wn * 32 + cr];
-      const double b1 = Bs[cur][kk + kr][wn * 32 + 16 + cr];
-      acc[0][0] = mfma64(b0, a0, acc[0][0]);
-      acc[0][1] = mfma64(b1, a0, acc[0][1]);
-      acc[1][0] = mfma64(b0, a1, acc[1][0]);
-      acc[1][1] = mfma64(b1, a1, acc[1][1]);
+      double a[FM], b[FN];
+#pragma unroll
+      for (int x = 0; x < FM; ++x) a[x] = As[cur][kk + kr][wm * (BM / 2) + x * 16 + cr];
+#pragma unroll
+      for (int y = 0; y < FN; ++y) b[y] = Bs[cur][kk + kr][wn * (BN / 2) + y * 16 + cr];
+#pragma unroll
+      for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfma64(b[y], a[x], acc[x][y]);
     }
     if (t + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
   // v_mfma_f64_16x16x4f64 leaves D(row = (lane>>4) + 4r, col = lane&15) in
   // register r of each lane; D is C^T here, so
-  // acc[x][y][r] = C(row = m0 + wm*32 + x*16 + (lane&15),
-  //                  col = n0 + wn*32 + y*16 + (lane>>4) + 4r)
+  // acc[x][y][r] = C(row = m0 + wm*BM/2 + x*16 + (lane&15),
+  //                  col = n0 + wn*BN/2 + y*16 + (lane>>4) + 4r)
 #pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    const int row = m0 + wm * 32 + x * 16 + cr;
+  for (int x = 0; x < FM; ++x) {
+    const int row = m0 + wm * (BM / 2) + x * 16 + cr;
     if (row >= M) continue;
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < FN; ++y) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int col = n0 + wn * 32 + y * 16 + kr + 4 * r;
+        const int col = n0 + wn * (BN / 2) + y * 16 + kr + 4 * r;
         if (col < N) {
           double* p = C + row + (int64_t)col * ldc;
           double v = alpha * acc[x][y][r];
@@ -144,12 +164,22 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ 
   }
 }
 
-template <bool TA, bool TB>
+template <bool TA, bool TB, int BM, int BN>
 void launch(hipStream_t st, dim3 grid, int M, int N, int K, int kper, const double* A,
             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
             int64_t zstride, double alpha, double beta) {
-  hipLaunchKernelGGL((k_dgemm<TA, TB>), grid, dim3(256), 0, st, M, N, K, kper, A, lda, B,
-                     ldb, C, ldc, zstride, alpha, beta);
+  hipLaunchKernelGGL((k_dgemm<TA, TB, BM, BN>), grid, dim3(256), 0, st, M, N, K, kper, A, lda,
+                     B, ldb, C, ldc, zstride, alpha, beta);
+}
+
+template <int BM, int BN>
+void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, int kper,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+              int64_t ldc, int64_t zs, double al, double be) {
+  if (!ta && !tb) launch<false, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (ta && !tb) launch<true, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (!ta && tb) launch<false, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else launch<true, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
 }  // namespace
@@ -160,13 +190,19 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
                 size_t splitws_elems) {
   (void)prec;
   if (M <= 0 || N <= 0) return hipSuccess;
-  const int tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
+  // 128 x 128 tiles when the output, or the output times a split of K,
+  // gives enough workgroups; else 64 x 64.  Long reductions are split over
+  // blockIdx.z until about two workgroups per CU are in flight.
+  const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+  const bool big = t128 >= 384 || (splitws && K >= 2048 && t128 * std::min(8, K / 512) >= 384);
+  const int BMs = big ? 128 : 64, BNs = big ? 128 : 64;
+  const int tm = (M + BMs - 1) / BMs, tn = (N + BNs - 1) / BNs;
   const int tiles = tm * tn;
   int splits = 1;
   if (splitws && tiles < 512 && K >= 1024) {
-    splits = (1024 + tiles - 1) / tiles;
-    splits = min(splits, K / 512);
-    splits = min(splits, kMaxSplitK);
+    splits = (512 + tiles - 1) / tiles;
+    splits = std::min(splits, K / 512);
+    splits = std::min(splits, kMaxSplitK);
     while (splits > 1 && (size_t)splits * M * N > splitws_elems) --splits;
     if (splits < 1) splits = 1;
   }
@@ -186,10 +222,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     be = 0.0;
   }
   const int slot = prof_mark(st);
-  if (!ta && !tb) launch<false, false>(st, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  else if (ta && !tb) launch<true, false>(st, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  else if (!ta && tb) launch<false, true>(st, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  else launch<true, true>(st, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  if (big) launch_t<128, 128>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else launch_t<64, 64>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   prof_done(st, slot, ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN),
             2.0 * M * N * (double)K);
   hipError_t e = hipGetLastError();
