@@ -41,11 +41,15 @@ extern "C" {
  * are always stored in FP64.  RANDUTV_FP32: operands rounded to FP32, FP32
  * MFMA with FP32 accumulation.  RANDUTV_BF16X3: each operand split as
  * x ~ hi + lo with hi = bf16(x), lo = bf16(x - hi); products hi*hi + hi*lo
- * + lo*hi on BF16 MFMA with FP32 accumulation. */
+ * + lo*hi on BF16 MFMA with FP32 accumulation.  RANDUTV_BF16X3_FP32: BF16x3
+ * for the sampling products (their rounding only perturbs the sampled
+ * subspace, never the exactness of A = U T V^T, since the transforms are
+ * built from it in FP64) and FP32 for the two trailing updates. */
 typedef enum {
   RANDUTV_FP64 = 0,
   RANDUTV_FP32 = 1,
-  RANDUTV_BF16X3 = 2
+  RANDUTV_BF16X3 = 2,
+  RANDUTV_BF16X3_FP32 = 3
 } randutv_prec;
 
 /* Flags of randutv_factor. */
@@ -128,7 +132,7 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q,
  * memory, op(X) = X^T when tX != 0, inner products in `prec` arithmetic.
  * C is M x N, op(A) is M x K, op(B) is K x N.  work (may be NULL) enables a
  * split of long K: any size, used up to 8*M*N doubles.  Arguments 1..12 are
- * validated (-i on error). */
+ * validated (-i on error); prec is RANDUTV_FP64, _FP32 or _BF16X3. */
 int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                  double* C, int64_t ldc, void* work, size_t work_bytes, void* stream);

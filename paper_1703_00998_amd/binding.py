@@ -17,8 +17,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librandutv.so")
 
-RANDUTV_FP64, RANDUTV_FP32, RANDUTV_BF16X3 = 0, 1, 2
-PREC = {"fp64": RANDUTV_FP64, "fp32": RANDUTV_FP32, "bf16x3": RANDUTV_BF16X3}
+RANDUTV_FP64, RANDUTV_FP32, RANDUTV_BF16X3, RANDUTV_BF16X3_FP32 = 0, 1, 2, 3
+PREC = {"fp64": RANDUTV_FP64, "fp32": RANDUTV_FP32, "bf16x3": RANDUTV_BF16X3,
+        "bf16x3_fp32": RANDUTV_BF16X3_FP32}
 FORM_U, FORM_V = 1, 2
 
 _lib = None
@@ -82,7 +83,7 @@ def profile_begin():
     _check(lib().randutv_profile_begin(), "randutv_profile_begin")
 
 
-def profile_end(max_classes=16):
+def profile_end(max_classes=32):
     """Per kernel class: {name: (milliseconds, algorithmic flops, launches)}."""
     ms = (ctypes.c_double * max_classes)()
     fl = (ctypes.c_double * max_classes)()

@@ -26,10 +26,14 @@ constexpr int kMaxSplitK = 8;
 
 // Arithmetic of the thin-matrix products (values of randutv_prec).
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
+// randutv_prec value of the mixed mode: BF16x3 sampling, FP32 updates.
+constexpr int kPrecMixed = 3;
 
 // ---------------------------------------------------------------- timing
-enum ProfClass { PC_GEMM_NN, PC_GEMM_TN, PC_GEMM_NT, PC_GEMM_TT, PC_SPLITK, PC_PANEL, PC_SVD,
-                 PC_COUNT };
+// Profiling classes: thin GEMMs per arithmetic (FP64, FP32, BF16x3) and
+// transpose case (class = 4*prec + 2*tb + ta), then the other kernels.
+enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
+                 PC_SPLITK = 12, PC_PANEL, PC_SVD, PC_COUNT };
 bool prof_on();
 int prof_mark(hipStream_t st);  // start event; returns a slot or -1 when off
 void prof_done(hipStream_t st, int slot, int cls, double flops);

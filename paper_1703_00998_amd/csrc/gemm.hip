@@ -15,33 +15,83 @@
 // coalesced stores).  Long reductions are split over blockIdx.z into FP64
 // partials that a second kernel sums in a fixed order (bit-reproducible).
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
 namespace rutv {
 namespace {
 
-constexpr int BK = 16, PAD = 2;
+constexpr int PAD = 2;
 
 __device__ inline v4d mfma64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline v4f mfma32(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline v4f mfmabf(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int P>
+struct Cfg;
+template <>
+struct Cfg<PREC_FP64> {
+  static constexpr int BK = 16;
+};
+template <>
+struct Cfg<PREC_FP32> {
+  static constexpr int BK = 16;
+};
+template <>
+struct Cfg<PREC_BF16X3> {
+  static constexpr int BK = 32;
+};
+
+// LDS slabs of one K step, per arithmetic.  FP64/FP32: [k][i] with i
+// contiguous (MFMA 16x16x4 takes one element per lane).  BF16 hi/lo pairs:
+// [k/8][i][k%8] so that each lane reads its 8 consecutive k values of row i
+// (the bf16 MFMA operand) as one 16-byte load.
+template <int P, int BM, int BN>
+struct Slabs;
+template <int BM, int BN>
+struct Slabs<PREC_FP64, BM, BN> {
+  double A[2][16][BM + PAD];
+  double B[2][16][BN + PAD];
+};
+template <int BM, int BN>
+struct Slabs<PREC_FP32, BM, BN> {
+  float A[2][16][BM + PAD];
+  float B[2][16][BN + PAD];
+};
+template <int BM, int BN>
+struct Slabs<PREC_BF16X3, BM, BN> {
+  alignas(16) __bf16 Ah[2][4][BM][8];
+  alignas(16) __bf16 Al[2][4][BM][8];
+  alignas(16) __bf16 Bh[2][4][BN][8];
+  alignas(16) __bf16 Bl[2][4][BN][8];
+};
+
 // BM x BN output tile per 256-thread workgroup; 2 x 2 waves, each owning a
 // (BM/2) x (BN/2) quarter as (BM/32) x (BN/32) MFMA 16 x 16 blocks.  The
 // occupancy hint keeps registers low enough for two workgroups per CU, so
-// one workgroup's loads overlap the other's MFMAs (measured: 128 x 128 tiles
-// at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26 without the hint).
-template <bool TA, bool TB, int BM, int BN>
-__global__ __launch_bounds__(256, 2) void k_dgemm(int M, int N, int K, int kper,
-                                               const double* __restrict__ A, int64_t lda,
-                                               const double* __restrict__ B, int64_t ldb,
-                                               double* __restrict__ C, int64_t ldc,
-                                               int64_t zstride, double alpha, double beta) {
-  constexpr int FM = BM / 32, FN = BN / 32;       // MFMA blocks per wave
+// one workgroup's loads overlap the other's MFMAs (measured in FP64: 128 x
+// 128 tiles at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26 without it).
+// Operands are FP64 in memory for every arithmetic; the loader converts.
+template <int P, bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, int kper,
+                                                 const double* __restrict__ A, int64_t lda,
+                                                 const double* __restrict__ B, int64_t ldb,
+                                                 double* __restrict__ C, int64_t ldc,
+                                                 int64_t zstride, double alpha, double beta) {
+  constexpr int BK = Cfg<P>::BK;
+  constexpr int FM = BM / 32, FN = BN / 32;              // MFMA blocks per wave
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread
-  __shared__ double As[2][BK][BM + PAD];
-  __shared__ double Bs[2][BK][BN + PAD];
+  __shared__ Slabs<P, BM, BN> sl;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -82,21 +132,39 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int M, int N, int K, int kper,
     for (int r = 0; r < LA; ++r) {
       int i, k;
       a_idx(r, i, k);
-      As[buf][k][i] = ra[r];
+      if constexpr (P == PREC_FP64) sl.A[buf][k][i] = ra[r];
+      else if constexpr (P == PREC_FP32) sl.A[buf][k][i] = (float)ra[r];
+      else {
+        const float x = (float)ra[r];
+        const __bf16 h = (__bf16)x;
+        sl.Ah[buf][k >> 3][i][k & 7] = h;
+        sl.Al[buf][k >> 3][i][k & 7] = (__bf16)(x - (float)h);
+      }
     }
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       int k, j;
       b_idx(r, k, j);
-      Bs[buf][k][j] = rb[r];
+      if constexpr (P == PREC_FP64) sl.B[buf][k][j] = rb[r];
+      else if constexpr (P == PREC_FP32) sl.B[buf][k][j] = (float)rb[r];
+      else {
+        const float x = (float)rb[r];
+        const __bf16 h = (__bf16)x;
+        sl.Bh[buf][k >> 3][j][k & 7] = h;
+        sl.Bl[buf][k >> 3][j][k & 7] = (__bf16)(x - (float)h);
+      }
     }
   };
 
-  v4d acc[FM][FN];
+  using AccT = typename std::conditional<P == PREC_FP64, v4d, v4f>::type;
+  AccT acc[FM][FN], acc2[FM][FN];
 #pragma unroll
   for (int x = 0; x < FM; ++x)
 #pragma unroll
-    for (int y = 0; y < FN; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < FN; ++y) {
+      acc[x][y] = AccT{0, 0, 0, 0};
+      acc2[x][y] = AccT{0, 0, 0, 0};
+    }
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
@@ -108,25 +176,51 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int M, int N, int K, int kper,
   for (int t = 0; t < nk; ++t) {
     const int cur = t & 1;
     if (t + 1 < nk) load(kbeg + (t + 1) * BK);
+    if constexpr (P == PREC_BF16X3) {
+      v8bf ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      double a[FM], b[FN];
+      for (int x = 0; x < FM; ++x) {
+        ah[x] = *(const v8bf*)&sl.Ah[cur][kr][wm * (BM / 2) + x * 16 + cr][0];
+        al[x] = *(const v8bf*)&sl.Al[cur][kr][wm * (BM / 2) + x * 16 + cr][0];
+      }
 #pragma unroll
-      for (int x = 0; x < FM; ++x) a[x] = As[cur][kk + kr][wm * (BM / 2) + x * 16 + cr];
-#pragma unroll
-      for (int y = 0; y < FN; ++y) b[y] = Bs[cur][kk + kr][wn * (BN / 2) + y * 16 + cr];
+      for (int y = 0; y < FN; ++y) {
+        bh[y] = *(const v8bf*)&sl.Bh[cur][kr][wn * (BN / 2) + y * 16 + cr][0];
+        bl[y] = *(const v8bf*)&sl.Bl[cur][kr][wn * (BN / 2) + y * 16 + cr][0];
+      }
 #pragma unroll
       for (int x = 0; x < FM; ++x)
 #pragma unroll
-        for (int y = 0; y < FN; ++y) acc[x][y] = mfma64(b[y], a[x], acc[x][y]);
+        for (int y = 0; y < FN; ++y) {
+          acc[x][y] = mfmabf(bh[y], ah[x], acc[x][y]);
+          acc2[x][y] = mfmabf(bh[y], al[x], acc2[x][y]);
+          acc2[x][y] = mfmabf(bl[y], ah[x], acc2[x][y]);
+        }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        typename std::conditional<P == PREC_FP64, double, float>::type a[FM], b[FN];
+#pragma unroll
+        for (int x = 0; x < FM; ++x) a[x] = sl.A[cur][kk + kr][wm * (BM / 2) + x * 16 + cr];
+#pragma unroll
+        for (int y = 0; y < FN; ++y) b[y] = sl.B[cur][kk + kr][wn * (BN / 2) + y * 16 + cr];
+#pragma unroll
+        for (int x = 0; x < FM; ++x)
+#pragma unroll
+          for (int y = 0; y < FN; ++y) {
+            if constexpr (P == PREC_FP64) acc[x][y] = mfma64(b[y], a[x], acc[x][y]);
+            else acc[x][y] = mfma32(b[y], a[x], acc[x][y]);
+          }
+      }
     }
     if (t + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
-  // v_mfma_f64_16x16x4f64 leaves D(row = (lane>>4) + 4r, col = lane&15) in
-  // register r of each lane; D is C^T here, so
-  // acc[x][y][r] = C(row = m0 + wm*BM/2 + x*16 + (lane&15),
-  //                  col = n0 + wn*BN/2 + y*16 + (lane>>4) + 4r)
+  // The MFMA computes D = C^T.  v_mfma_f64_16x16x4f64 leaves D(row =
+  // (lane>>4) + 4r, col = lane&15) in register r; the f32 and bf16 MFMAs
+  // leave D(row = 4(lane>>4) + r, col = lane&15).  So C(row, col) with
+  // row = m0 + wm*BM/2 + x*16 + (lane&15) and col = n0 + wn*BN/2 + y*16 +
+  // ((lane>>4) + 4r) for FP64, (4(lane>>4) + r) otherwise.
 #pragma unroll
   for (int x = 0; x < FM; ++x) {
     const int row = m0 + wm * (BM / 2) + x * 16 + cr;
@@ -135,10 +229,13 @@ __global__ __launch_bounds__(256, 2) void k_dgemm(int M, int N, int K, int kper,
     for (int y = 0; y < FN; ++y) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int col = n0 + wn * (BN / 2) + y * 16 + kr + 4 * r;
+        const int col = n0 + wn * (BN / 2) + y * 16 + (P == PREC_FP64 ? kr + 4 * r : 4 * kr + r);
         if (col < N) {
           double* p = C + row + (int64_t)col * ldc;
-          double v = alpha * acc[x][y][r];
+          double v;
+          if constexpr (P == PREC_BF16X3) v = (double)acc[x][y][r] + (double)acc2[x][y][r];
+          else v = (double)acc[x][y][r];
+          v *= alpha;
           if (beta != 0.0) v += beta * *p;
           *p = v;
         }
@@ -164,22 +261,30 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ 
   }
 }
 
-template <bool TA, bool TB, int BM, int BN>
+template <int P, bool TA, bool TB, int BM, int BN>
 void launch(hipStream_t st, dim3 grid, int M, int N, int K, int kper, const double* A,
             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
             int64_t zstride, double alpha, double beta) {
-  hipLaunchKernelGGL((k_dgemm<TA, TB, BM, BN>), grid, dim3(256), 0, st, M, N, K, kper, A, lda,
+  hipLaunchKernelGGL((k_gemm<P, TA, TB, BM, BN>), grid, dim3(256), 0, st, M, N, K, kper, A, lda,
                      B, ldb, C, ldc, zstride, alpha, beta);
 }
 
-template <int BM, int BN>
+template <int P, int BM, int BN>
 void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, int kper,
               const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
               int64_t ldc, int64_t zs, double al, double be) {
-  if (!ta && !tb) launch<false, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (ta && !tb) launch<true, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (!ta && tb) launch<false, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else launch<true, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  if (!ta && !tb) launch<P, false, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (ta && !tb) launch<P, true, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (!ta && tb) launch<P, false, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else launch<P, true, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+}
+
+template <int P>
+void launch_p(hipStream_t st, bool big, bool ta, bool tb, dim3 grid, int M, int N, int K,
+              int kper, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+              int64_t ldc, int64_t zs, double al, double be) {
+  if (big) launch_t<P, 128, 128>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else launch_t<P, 64, 64>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
 }  // namespace
@@ -188,8 +293,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc, double* splitws,
                 size_t splitws_elems) {
-  (void)prec;
   if (M <= 0 || N <= 0) return hipSuccess;
+  const int BK = prec == PREC_BF16X3 ? 32 : 16;
   // 128 x 128 tiles when the output, or the output times a split of K,
   // gives enough workgroups; else 64 x 64.  Long reductions are split over
   // blockIdx.z until about two workgroups per CU are in flight.
@@ -222,9 +327,13 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     be = 0.0;
   }
   const int slot = prof_mark(st);
-  if (big) launch_t<128, 128>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  else launch_t<64, 64>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  prof_done(st, slot, ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN),
+  if (prec == PREC_FP32)
+    launch_p<PREC_FP32>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else if (prec == PREC_BF16X3)
+    launch_p<PREC_BF16X3>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else
+    launch_p<PREC_FP64>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  prof_done(st, slot, 4 * (int)prec + (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN)),
             2.0 * M * N * (double)K);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;

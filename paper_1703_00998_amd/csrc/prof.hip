@@ -31,8 +31,11 @@ hipEvent_t take_event() {
   return e;
 }
 
-const char* kNames[PC_COUNT] = {"gemm_nn", "gemm_tn", "gemm_nt", "gemm_tt",
-                                "splitk_reduce", "panel_qr", "small_svd"};
+const char* kNames[PC_COUNT] = {
+    "gemm_nn",        "gemm_tn",        "gemm_nt",        "gemm_tt",
+    "gemm_nn_fp32",   "gemm_tn_fp32",   "gemm_nt_fp32",   "gemm_tt_fp32",
+    "gemm_nn_bf16x3", "gemm_tn_bf16x3", "gemm_nt_bf16x3", "gemm_tt_bf16x3",
+    "splitk_reduce",  "panel_qr",       "small_svd"};
 
 }  // namespace
 

@@ -121,7 +121,7 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, uns
   if (m < n) return RANDUTV_E_UNSUPPORTED;
   if (b < 1 || b > kMaxB) return -3;
   if (q < 0 || q > 16) return -4;
-  if (prec < 0 || prec > 2) return -5;
+  if (prec < 0 || prec > 3) return -5;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -6;
   if (!bytes) return -7;
   *bytes = make_layout(m, n, b).total;
@@ -154,7 +154,7 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   const bool formU = flags & RANDUTV_FORM_U, formV = flags & RANDUTV_FORM_V;
   if (formU && (!U || ldu < m)) return -6;
   if (formV && (!V || ldv < n)) return -7;
-  if (prec < 0 || prec > 2) return -10;
+  if (prec < 0 || prec > 3) return -10;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -11;
   if (!work || ((uintptr_t)work & 255)) return -12;
   const Layout L = make_layout(m, n, b);
@@ -174,7 +174,9 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   int* jstatus = ints + s;
   PanelWork pw;
   panel_work_carve(base + L.panel, (int)b, &pw);
-  const Prec pr = (Prec)prec;
+  // Arithmetic of the sampling products (ps) and of the trailing updates (pu).
+  const Prec ps = prec == kPrecMixed ? PREC_BF16X3 : (Prec)prec;
+  const Prec pu = prec == kPrecMixed ? PREC_FP32 : (Prec)prec;
   const size_t se = L.split_elems;
   const int M = (int)m, N = (int)n, B = (int)b;
 
@@ -200,19 +202,19 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
     if (r0 + B < M && r0 + B < N) {
       const double* Gi = G + (int64_t)i * b * ldg;
       // Sampling matrix Y = (X^T X)^q X^T G_i.
-      HIPCHK(gemm(st, pr, true, false, Ni, B, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se));
+      HIPCHK(gemm(st, ps, true, false, Ni, B, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se));
       for (int it = 0; it < q; ++it) {
-        HIPCHK(gemm(st, pr, false, false, Mi, B, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se));
-        HIPCHK(gemm(st, pr, true, false, Ni, B, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
+        HIPCHK(gemm(st, ps, false, false, Mi, B, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se));
+        HIPCHK(gemm(st, ps, true, false, Ni, B, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
       }
       // [Vq, ~] = qr(Y)
       HIPCHK(panel_qr(st, Ni, B, Y, N, tauV, TwV, B, pw));
       HIPCHK(panel_extract(st, Ni, B, Y, N, Vh, N, nullptr, 0));
       // T(:, J) = T(:, J) Vq, all m rows.
       double* TJ = T + (int64_t)r0 * ldt;
-      HIPCHK(gemm(st, pr, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
+      HIPCHK(gemm(st, pu, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
       HIPCHK(gemm(st, PREC_FP64, false, false, M, B, B, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
-      HIPCHK(gemm(st, pr, false, true, M, Ni, B, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
+      HIPCHK(gemm(st, pu, false, true, M, Ni, B, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
       if (formV) {
         double* VJ = V + (int64_t)r0 * ldv;
         HIPCHK(gemm(st, PREC_FP64, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, W, M, split, se));
@@ -226,9 +228,9 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
       // T([I2,I3], J3) = Uq^T T([I2,I3], J3)
       const int Nr = Ni - B;
       double* XJ3 = X + (int64_t)B * ldt;
-      HIPCHK(gemm(st, pr, true, false, B, Nr, Mi, 1.0, Uh, M, XJ3, ldt, 0.0, C, B, split, se));
+      HIPCHK(gemm(st, pu, true, false, B, Nr, Mi, 1.0, Uh, M, XJ3, ldt, 0.0, C, B, split, se));
       HIPCHK(gemm(st, PREC_FP64, true, false, B, Nr, B, 1.0, TwU, B, C, B, 0.0, C2, B, nullptr, 0));
-      HIPCHK(gemm(st, pr, false, false, Mi, Nr, B, -1.0, Uh, M, C2, B, 1.0, XJ3, ldt, nullptr, 0));
+      HIPCHK(gemm(st, pu, false, false, Mi, Nr, B, -1.0, Uh, M, C2, B, 1.0, XJ3, ldt, nullptr, 0));
       // U(:, [I2,I3]) = U(:, [I2,I3]) Uq
       if (formU) {
         double* UI = U + (int64_t)r0 * ldu;

@@ -49,6 +49,42 @@ def test_gemm_fp64_matches_numpy(B, M, N, K, ta, tb):
     np.testing.assert_allclose(got, ref, rtol=0, atol=scale * (np.abs(ref).max() + 1))
 
 
+SPLIT_TOL = {"fp32": 2 ** -24, "bf16x3": 2 ** -16}
+
+
+@pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_gemm_split_precision_error_bound(B, M, N, K, ta, tb, prec):
+    """Split-precision products (FP64 in and out): each entry's error is
+    bounded by a few units of the arithmetic's rounding times |a_i||b_j|
+    (FP32: operand rounding 2^-24 plus FP32 accumulation; BF16x3: the dropped
+    lo*lo term and the BF16 representation error, 2^-16 together), plus the
+    accumulation's sqrt(K) growth.  A lane-layout or hi/lo mistake gives
+    errors of order |a_i||b_j| and fails."""
+    print(f"gemm {prec} M={M} N={N} K={K} ta={ta} tb={tb}", flush=True)
+    rng = np.random.default_rng(M * 5 + N * 11 + K + (7 if prec == "fp32" else 13))
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    Bm = rng.standard_normal((N, K) if tb else (K, N))
+    A *= np.exp(rng.uniform(-3, 3, size=A.shape))  # spread of magnitudes
+    C0 = rng.standard_normal((M, N))
+    Aop = A.T if ta else A
+    Bop = Bm.T if tb else Bm
+    ref = 0.75 * (Aop @ Bop) - 0.5 * C0
+    dA, dB, dC = B.colmajor(A), B.colmajor(Bm), B.colmajor(C0)
+    ws = B.workspace(8 * M * N * 8)
+    B.randutv_gemm(dC, dA, dB, ta=ta, tb=tb, alpha=0.75, beta=-0.5, prec=prec, work=ws)
+    torch.cuda.synchronize()
+    got = _np(dC)
+    scale = np.outer(np.linalg.norm(Aop, axis=1), np.linalg.norm(Bop, axis=0))
+    tol = 0.75 * scale * (4 * SPLIT_TOL[prec] + 8 * 2 ** -24 * np.sqrt(max(K, 1)))
+    err = np.abs(got - ref)
+    assert np.all(err <= tol + 1e-14 * (np.abs(ref) + 1)), float((err / (tol + 1e-300)).max())
+    if prec == "bf16x3" and K >= 16:
+        # much better than one BF16 product: the error must sit well below 2^-9
+        assert float((err / (0.75 * scale + 1e-300)).max()) < 2 ** -12
+
+
 def _larft(V, tau):
     """Host reference compact-WY factor by the column recurrence
     T(0:j,j) = -tau_j T(0:j,0:j) V(:,0:j)^T v_j, T(j,j) = tau_j."""
