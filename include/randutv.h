@@ -143,10 +143,15 @@ int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, doub
  * convention), and the upper triangular compact-WY factor Tw (nb x nb, ld
  * ldtw, zeros below the diagonal) with H_0 H_1 ... H_{nb-1} = I - V Tw V^T
  * (eq. WYrepresentation).  Requires nb <= Mp <= 32768 and nb <= 256.
- * work: at least randutv_panel_work_size(nb) bytes, 256-byte aligned. */
-size_t randutv_panel_work_size(int64_t nb);
+ * Computed by CholeskyQR2 with Householder reconstruction when the panel is
+ * well conditioned, else by column-by-column Householder; *used_fallback
+ * (host pointer, may be NULL) reports which (1 = column-by-column).
+ * work: at least randutv_panel_work_size(Mp, nb) bytes, 256-byte aligned
+ * (-9 otherwise).  Waits for completion. */
+size_t randutv_panel_work_size(int64_t Mp, int64_t nb);
 int randutv_panel_qr(int64_t Mp, int64_t nb, double* P, int64_t ldp, double* tau, double* Tw,
-                     int64_t ldtw, void* work, size_t work_bytes, void* stream);
+                     int64_t ldtw, int* used_fallback, void* work, size_t work_bytes,
+                     void* stream);
 
 /* SVD of `count` small square blocks (Figure "The algorithm randUTV",
  * [Us, Ds, Vs] = svd(R)): matrix i has size nbs[i] (host array, each

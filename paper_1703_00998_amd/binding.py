@@ -52,9 +52,10 @@ def lib():
     L.randutv_gemm.argtypes = [i32, i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl,
                                vp, i64, vp, sz, vp]
     L.randutv_gemm.restype = i32
-    L.randutv_panel_work_size.argtypes = [i64]
+    L.randutv_panel_work_size.argtypes = [i64, i64]
     L.randutv_panel_work_size.restype = sz
-    L.randutv_panel_qr.argtypes = [i64, i64, vp, i64, vp, vp, i64, vp, sz, vp]
+    L.randutv_panel_qr.argtypes = [i64, i64, vp, i64, vp, vp, i64, ctypes.POINTER(i32), vp, sz,
+                                   vp]
     L.randutv_panel_qr.restype = i32
     L.randutv_small_svd_work_size.argtypes = [i64, i64]
     L.randutv_small_svd_work_size.restype = sz
@@ -204,13 +205,19 @@ def randutv_gemm(C, A, B, ta=False, tb=False, alpha=1.0, beta=0.0, prec="fp64", 
 
 
 def randutv_panel_qr(P, tau, Tw):
-    """In-place Householder QR of the tall panel P; fills tau and Tw."""
+    """In-place Householder QR of the tall panel P; fills tau and Tw.
+    Returns True when the column-by-column path ran (ill-conditioned panel)."""
     Mp, nb = P.shape
-    need = int(lib().randutv_panel_work_size(nb))
+    need = int(lib().randutv_panel_work_size(Mp, nb))
+    if need == 0:
+        raise RandUTVError(f"randutv_panel_qr: unsupported panel shape {Mp} x {nb}")
     ws = workspace(need, P.device)
     wp, wb = _aligned_ptr(ws)
+    fb = ctypes.c_int32(0)
     _check(lib().randutv_panel_qr(Mp, nb, _ptr(P), _ld(P, Mp), _ptr(tau), _ptr(Tw),
-                                  _ld(Tw, Tw.shape[0]), wp, wb, _stream()), "randutv_panel_qr")
+                                  _ld(Tw, Tw.shape[0]), ctypes.byref(fb), wp, wb, _stream()),
+           "randutv_panel_qr")
+    return bool(fb.value)
 
 
 def randutv_small_svd(R, nbs):

@@ -23,6 +23,7 @@ constexpr int kPanelMaxRows = 256;
 constexpr unsigned kSpinLimit = 1u << 20;
 // Largest split-K factor of the thin GEMMs.
 constexpr int kMaxSplitK = 8;
+constexpr int kMaxSplitKSmall = 64;  // for outputs of at most 32 tiles of 64 x 64
 
 // Arithmetic of the thin-matrix products (values of randutv_prec).
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
@@ -36,6 +37,7 @@ enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
                  PC_SPLITK = 12, PC_PANEL, PC_SVD, PC_COUNT };
 bool prof_on();
 int prof_mark(hipStream_t st);  // start event; returns a slot or -1 when off
+void prof_suppress(int delta);  // +1 / -1 around launches timed by an enclosing mark
 void prof_done(hipStream_t st, int slot, int cls, double flops);
 
 // ---------------------------------------------------------------- GEMM
@@ -66,13 +68,39 @@ void panel_work_carve(void* base, int bmax, PanelWork* w);
 // layout: R on and above the diagonal, reflector tails below), tau[nb], and
 // the upper-triangular compact-WY factor Tw (nb x nb, ld = ldtw) with
 // H_0 ... H_{nb-1} = I - V Tw V^T.
+// Launched kernels return at once when `gate` is non-NULL and *gate == 0.
 hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp,
-                    double* tau, double* Tw, int64_t ldtw, const PanelWork& w);
+                    double* tau, double* Tw, int64_t ldtw, const PanelWork& w,
+                    const int* gate = nullptr);
 
 // V (Mp x nb, unit lower trapezoidal, explicit ones and zeros) from the
 // dgeqrf layout in P; R (nb x nb upper triangle, zeros below) to Rout.
 hipError_t panel_extract(hipStream_t st, int Mp, int nb, const double* P, int64_t ldp,
-                         double* V, int64_t ldv, double* Rout, int64_t ldr);
+                         double* V, int64_t ldv, double* Rout, int64_t ldr,
+                         const int* gate = nullptr);
+
+// Whole-panel Householder QR by CholeskyQR2 + Householder reconstruction,
+// with the column-by-column kernel as a device-gated fallback.
+struct HrWork {
+  double *G, *R1, *R1i, *R2, *R2i, *RF, *QT, *LU, *Ui, *Li, *US, *Wc, *Cc;  // 128^2 each
+  double* Q1;  // Mp_max x 128
+  double* P2;  // Mp_max x 128 (second block of a panel wider than 128)
+  int* flag;   // 1 when the fallback ran
+};
+size_t hr_work_bytes(int64_t Mp_max, int nb_max);
+void hr_work_carve(void* base, int64_t Mp_max, int nb_max, HrWork* w);
+// P (Mp x nb, ld ldp) is read (and only overwritten when the fallback runs);
+// V (Mp x nb) receives the unit-lower-trapezoidal reflectors with explicit
+// ones and zeros, Rout (nb x nb, may be NULL) the R factor with zeros
+// below, tau[nb] and Tw (upper, I - V Tw V^T = H_0 ... H_{nb-1}).
+// `split` (split_elems doubles) serves the split-K reductions.
+hipError_t panel_qr_hr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, double* V,
+                       int64_t ldv, double* Rout, int64_t ldr, double* tau, double* Tw,
+                       int64_t ldtw, const HrWork& hw, const PanelWork& pw, double* split,
+                       size_t split_elems);
+// P = [R above and on the diagonal; V below] (LAPACK dgeqrf layout).
+hipError_t pack_qr(hipStream_t st, int Mp, int nb, const double* V, int64_t ldv,
+                   const double* R, int64_t ldr, double* P, int64_t ldp);
 
 // ---------------------------------------------------------------- small SVD
 // Batched one-sided Jacobi SVD of `count` square matrices R_i (size nb_i,

@@ -305,9 +305,11 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   const int tiles = tm * tn;
   int splits = 1;
   if (splitws && tiles < 512 && K >= 1024) {
-    splits = (512 + tiles - 1) / tiles;
-    splits = std::min(splits, K / 512);
-    splits = std::min(splits, kMaxSplitK);
+    // Small outputs (Gram matrices of tall panels) split deeper.
+    const bool small = tiles <= 32;
+    splits = ((small ? 1024 : 512) + tiles - 1) / tiles;
+    splits = std::min(splits, K / (small ? 256 : 512));
+    splits = std::min(splits, small ? kMaxSplitKSmall : kMaxSplitK);
     while (splits > 1 && (size_t)splits * M * N > splitws_elems) --splits;
     if (splits < 1) splits = 1;
   }

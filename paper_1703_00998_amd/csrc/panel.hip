@@ -43,6 +43,7 @@ struct PanelArgs {
   double* red;
   unsigned* bar;
   int* err;
+  const int* gate;  // run only if NULL or *gate != 0 (read uniformly by every thread)
 };
 
 __device__ inline void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
@@ -87,6 +88,7 @@ __device__ inline double sum16(double v) {
 }
 
 __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
+  if (a.gate && *a.gate == 0) return;  // uniform over the grid: no barrier is entered
   __shared__ double S[PNB][kPanelMaxRows];  // sub-panel slice of my rows
   __shared__ double sred[PNB][MAXB];        // reduced Vs^T [V_prev | Vs | P_rest]
   __shared__ double sZ[MAXB][PNB];          // (V_prev^T Vs) Ts
@@ -314,6 +316,7 @@ struct PanelArgs2 {
   double* red;
   unsigned* bar;
   int* err;
+  const int* gate;
   double* gram;  // 2 * kPanelMaxWG * 256 Gram partials
   double* qtop;  // kPanelNB^2 published top rows of Q
 };
@@ -595,6 +598,7 @@ __device__ bool subpanel_cholqr_hr(double* S, int c0, int pw, int ldS, int rb, i
 }
 
 __global__ __launch_bounds__(256) void k_panel_lds(PanelArgs2 a) {
+  if (a.gate && *a.gate == 0) return;  // uniform over the grid: no barrier is entered
   extern __shared__ double smem[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int w = blockIdx.x;
@@ -895,7 +899,8 @@ __global__ void k_init_sync(unsigned* bar) {
 
 __global__ void k_extract(int Mp, int nb, const double* __restrict__ P, int64_t ldp,
                           double* __restrict__ V, int64_t ldv, double* __restrict__ R,
-                          int64_t ldr) {
+                          int64_t ldr, const int* gate) {
+  if (gate && *gate == 0) return;
   const int64_t total = (int64_t)Mp * nb;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -934,7 +939,7 @@ void panel_work_carve(void* base, int bmax, PanelWork* w) {
 }
 
 hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, double* tau,
-                    double* Tw, int64_t ldtw, const PanelWork& w) {
+                    double* Tw, int64_t ldtw, const PanelWork& w, const int* gate) {
   if (nb <= 0) return hipSuccess;
   if (nb > MAXB || Mp < nb) return hipErrorInvalidValue;
   static int cu_count = 0;
@@ -966,7 +971,7 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
       const size_t shmem = ((size_t)(nb + PNB) * ldS + fixed) * sizeof(double);
       hipLaunchKernelGGL(k_init_sync, dim3(1), dim3(64), 0, st, w.bar);
       PanelArgs2 a{Mp, nb, nwg, chunk, ldS, nwg > 1 ? 1 : 0, P, ldp, tau, Tw, ldtw, w.part,
-                   w.bcast, w.bpart, w.red, w.bar, w.err, w.gram, w.qtop};
+                   w.bcast, w.bpart, w.red, w.bar, w.err, gate, w.gram, w.qtop};
       void* args[] = {&a};
       const int slot = prof_mark(st);
       hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel_lds, dim3(nwg), dim3(256),
@@ -983,7 +988,7 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
   nwg = (Mp + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_init_sync, dim3(1), dim3(64), 0, st, w.bar);
   PanelArgs a{Mp, nb, nwg, chunk, P, ldp, tau, Tw, ldtw, w.part, w.bcast, w.bpart, w.red,
-              w.bar, w.err};
+              w.bar, w.err, gate};
   void* args[] = {&a};
   const int slot = prof_mark(st);
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel, dim3(nwg), dim3(256), args, 0, st);
@@ -992,12 +997,12 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
 }
 
 hipError_t panel_extract(hipStream_t st, int Mp, int nb, const double* P, int64_t ldp,
-                         double* V, int64_t ldv, double* Rout, int64_t ldr) {
+                         double* V, int64_t ldv, double* Rout, int64_t ldr, const int* gate) {
   const int64_t total = (int64_t)Mp * nb;
   if (total == 0) return hipSuccess;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   hipLaunchKernelGGL(k_extract, dim3(blocks), dim3(256), 0, st, Mp, nb, P, ldp, V, ldv, Rout,
-                     ldr);
+                     ldr, gate);
   return hipGetLastError();
 }
 

@@ -1,0 +1,620 @@
+// Householder QR of a whole tall panel by CholeskyQR2 and Householder
+// reconstruction (Section 2.4, eqs. unpivQR and WYrepresentation).
+//
+// The reflectors of an unpivoted Householder QR are fixed by the orthonormal
+// factor Q alone: with S = diag(s_k), s_k = -sign of the k-th pivot, the LU
+// factorization Q - [S; 0] = L U (no pivoting needed: every |u_kk| >= 1)
+// gives V = L (unit lower trapezoidal), Tw = -U S L1^-T (L1 = top nb x nb
+// block of L) and R_householder = S R, so that (I - V Tw V^T)(:, 1:nb) = Q S.
+// The signs follow LAPACK dlarfg (beta = -sign(alpha) ||x||, sign(0) = +1),
+// so the result is the dgeqrf factorization up to rounding.
+//
+// Q comes from CholeskyQR2 (Gram, Cholesky, Q1 = P R1^-1, repeated once), so
+// the whole panel costs four tall MFMA products over its Mp rows plus three
+// nb x nb factorizations, instead of nb dependent column steps.  CholeskyQR2
+// needs kappa(P) well below eps^-1/2: the Cholesky kernels and the LU raise
+// a device flag when a pivot says otherwise (or when a column tail is
+// exactly zero, where dlarfg takes tau = 0), and then the column-by-column
+// cooperative kernel refactors the panel, gated on that flag, so no host
+// round trip is needed.
+//
+// The nb x nb work runs in one workgroup of 8 waves on 16 x 16 FP64 MFMA
+// tiles (matrix padded to a multiple of 16 with an identity block): right-
+// looking blocked factorizations whose 16 x 16 diagonal blocks are factored
+// by one wave in LDS, with the triangular inverses built alongside, block
+// column by block column.
+#include <algorithm>
+
+#include "common.h"
+
+namespace rutv {
+namespace {
+
+constexpr int TS = 16;         // tile size
+constexpr int kWaves = 8;      // waves of the single-workgroup kernels
+constexpr int kThreads = 64 * kWaves;
+constexpr int kBlk = 128;      // widest block factored in LDS (wider panels: two blocks)
+constexpr int LDA = kBlk + 1;  // LDS leading dimension (odd: spreads the banks)
+
+__device__ inline v4d mfma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// acc += op(A) op(B) for 16 x 16 tiles (K = 16).  Tiles are column-major with
+// leading dimensions lda / ldb; TA / TB take the transpose.  MFMA operand
+// layout: A(i, k) from lane i + 16k, B(k, j) from lane j + 16k; result
+// D((lane>>4) + 4r, lane & 15) in register r.
+template <bool TA, bool TB>
+__device__ inline v4d tile_mma(v4d acc, const double* A, int lda, const double* B, int ldb) {
+  const int l = threadIdx.x & 63;
+  const int i = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int kk = 0; kk < TS; kk += 4) {
+    const int k = kk + kq;
+    const double a = TA ? A[k + i * lda] : A[i + k * lda];
+    const double b = TB ? B[i + k * ldb] : B[k + i * ldb];
+    acc = mfma(a, b, acc);
+  }
+  return acc;
+}
+
+__device__ inline v4d tile_load(const double* X, int ld) {
+  const int l = threadIdx.x & 63;
+  v4d v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = X[((l >> 4) + 4 * r) + (l & 15) * ld];
+  return v;
+}
+
+__device__ inline void tile_store(double* X, int ld, v4d v) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X[((l >> 4) + 4 * r) + (l & 15) * ld] = v[r];
+}
+
+__device__ inline v4d vzero() { return v4d{0.0, 0.0, 0.0, 0.0}; }
+
+// acc += A * b, where b is a register tile in the result layout (register r
+// of lane l holds b((l>>4) + 4r, l & 15)), which is exactly the MFMA B-operand
+// layout for k = 4r + (l>>4); A is a 16 x 16 tile (ld lda).
+__device__ inline v4d mma_reg_b(v4d acc, const double* A, int lda, v4d b) {
+  const int l = threadIdx.x & 63;
+  const int i = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc = mfma(A[i + (4 * r + kq) * lda], b[r], acc);
+  return acc;
+}
+
+// Inverse of the upper-triangular 16 x 16 tile U into X (both column-major,
+// leading dimensions ldu / ldx) by one wave: lane j < 16 back-substitutes
+// column j.
+__device__ void tile_inv_upper(const double* U, int ldu, double* X, int ldx) {
+  const int l = threadIdx.x & 63;
+  if (l < TS) {
+    const int j = l;
+    double x[TS];
+#pragma unroll
+    for (int i = 0; i < TS; ++i) x[i] = 0.0;
+#pragma unroll
+    for (int i = TS - 1; i >= 0; --i) {
+      if (i <= j) {
+        double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = i + 1; k < TS; ++k) s -= U[i + k * ldu] * x[k];
+        x[i] = s / U[i + i * ldu];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < TS; ++i) X[i + j * ldx] = x[i];
+  }
+}
+
+// Inverse of the unit-lower-triangular 16 x 16 tile L (diagonal taken as 1,
+// whatever is stored there) into X by one wave.
+__device__ void tile_inv_unit_lower(const double* L, int ldl, double* X, int ldx) {
+  const int l = threadIdx.x & 63;
+  if (l < TS) {
+    const int j = l;
+    double x[TS];
+#pragma unroll
+    for (int i = 0; i < TS; ++i) {
+      double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= L[i + k * ldl] * x[k];
+      x[i] = (i < j) ? 0.0 : s;
+    }
+#pragma unroll
+    for (int i = 0; i < TS; ++i) X[i + j * ldx] = x[i];
+  }
+}
+
+// The whole (padded) matrix of a single-workgroup kernel lives in LDS.
+struct Smem {
+  double A[kBlk * LDA];  // column-major, leading dimension LDA
+  double D[TS * 17];     // inverse of the current diagonal tile (ld 17)
+  double D2[TS * 17];
+  double red[kWaves];
+  double sgn[kBlk];
+  int fail;
+};
+
+__device__ inline double* tile(Smem& sm, int it, int jt) { return sm.A + it * TS + jt * TS * LDA; }
+
+__device__ inline double block_max(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < kWaves; ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// (a, b) with 0 <= a <= b < n from a linear index over the upper triangle.
+__device__ inline void upper_pair(int t, int n, int& a, int& b) {
+  a = 0;
+  while (t >= n - a) {
+    t -= n - a;
+    ++a;
+  }
+  b = a + t;
+}
+
+// Right-looking blocked upper Cholesky A = R^T R in place (nt tiles).  A
+// pivot at or below thr (a real column, index < n) marks failure and is
+// replaced by 1 so that the factorization stays finite.
+__device__ void chol_lds(Smem& sm, int n, int nt, double thr) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nbp = nt * TS;
+  for (int kt = 0; kt < nt; ++kt) {
+    const int k0 = kt * TS;
+    double* Akk = tile(sm, kt, kt);
+    if (wave == 0) {
+      bool bad = false;
+      for (int c = 0; c < TS; ++c) {
+        double d = Akk[c + c * LDA];
+        if (k0 + c < n && !(d > thr)) {
+          bad = true;
+          d = 1.0;
+        }
+        const double r = sqrt(d);
+        wave_sync();
+        if (lane >= c && lane < TS) Akk[c + lane * LDA] = (lane == c) ? r : Akk[c + lane * LDA] / r;
+        wave_sync();
+        for (int e = lane; e < TS * TS; e += 64) {
+          const int i = e & 15, j = e >> 4;
+          if (i > c && j >= i) Akk[i + j * LDA] -= Akk[c + i * LDA] * Akk[c + j * LDA];
+        }
+        wave_sync();
+      }
+      for (int e = lane; e < TS * TS; e += 64) {
+        const int i = e & 15, j = e >> 4;
+        if (i > j) Akk[i + j * LDA] = 0.0;
+      }
+      wave_sync();
+      tile_inv_upper(Akk, LDA, sm.D, 17);
+      if (bad && lane == 0) sm.fail = 1;
+    }
+    __syncthreads();
+    // row panel R(kt, jt) = R_kk^-T A(kt, jt)
+    for (int jt = kt + 1 + wave; jt < nt; jt += kWaves) {
+      double* At = tile(sm, kt, jt);
+      const v4d acc = tile_mma<true, false>(vzero(), sm.D, 17, At, LDA);
+      tile_store(At, LDA, acc);
+    }
+    __syncthreads();
+    // trailing A(it, jt) -= R(kt, it)^T R(kt, jt), kt < it <= jt
+    const int nr = nt - 1 - kt;
+    for (int t = wave; t < nr * (nr + 1) / 2; t += kWaves) {
+      int a, b;
+      upper_pair(t, nr, a, b);
+      const int it = kt + 1 + a, jt = kt + 1 + b;
+      double* At = tile(sm, it, jt);
+      v4d acc = tile_load(At, LDA);
+      const v4d p = tile_mma<true, false>(vzero(), tile(sm, kt, it), LDA, tile(sm, kt, jt), LDA);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] -= p[r];
+      tile_store(At, LDA, acc);
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    if (i > j) sm.A[i + j * LDA] = 0.0;
+  }
+  __syncthreads();
+}
+
+// In-place inverse of the upper-triangular matrix in sm.A, block row by block
+// row from the bottom: X(it, jt) = -R_ii^-1 sum_{k=it+1}^{jt} R(it,k) X(k,jt).
+__device__ void inv_upper_lds(Smem& sm, int nt) {
+  const int wave = threadIdx.x >> 6;
+  for (int it = nt - 1; it >= 0; --it) {
+    if (wave == 0) tile_inv_upper(tile(sm, it, it), LDA, sm.D, 17);
+    __syncthreads();
+    v4d x = vzero();
+    const int jt = it + 1 + wave;  // at most nt - 1 - it <= 7 tiles: one per wave
+    if (jt < nt) {
+      v4d z = vzero();
+      for (int k = it + 1; k <= jt; ++k)
+        z = tile_mma<false, false>(z, tile(sm, it, k), LDA, tile(sm, k, jt), LDA);
+      x = mma_reg_b(vzero(), sm.D, 17, z);
+    }
+    __syncthreads();
+    if (jt < nt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[r] = -x[r];
+      tile_store(tile(sm, it, jt), LDA, x);
+    }
+    if (wave == 0) tile_store(tile(sm, it, it), LDA, tile_load(sm.D, 17));
+    __syncthreads();
+  }
+}
+
+// In-place inverse of the unit-lower-triangular matrix in sm.A (diagonal
+// taken as 1), block row by block row from the top:
+// X(it, jt) = -L_ii^-1 sum_{k=jt}^{it-1} L(it,k) X(k,jt), jt < it.
+__device__ void inv_unit_lower_lds(Smem& sm, int nt) {
+  const int wave = threadIdx.x >> 6;
+  for (int it = 0; it < nt; ++it) {
+    if (wave == 0) tile_inv_unit_lower(tile(sm, it, it), LDA, sm.D, 17);
+    __syncthreads();
+    v4d x = vzero();
+    const int jt = wave;  // jt < it <= 7: one per wave
+    if (jt < it) {
+      v4d z = vzero();
+      for (int k = jt; k < it; ++k)
+        z = tile_mma<false, false>(z, tile(sm, it, k), LDA, tile(sm, k, jt), LDA);
+      x = mma_reg_b(vzero(), sm.D, 17, z);
+    }
+    __syncthreads();
+    if (jt < it) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[r] = -x[r];
+      tile_store(tile(sm, it, jt), LDA, x);
+    }
+    if (wave == 0) tile_store(tile(sm, it, it), LDA, tile_load(sm.D, 17));
+    __syncthreads();
+  }
+}
+
+// Upper Cholesky G = R^T R of an n x n Gram matrix (n <= 128, padded to
+// nbp = 16 nt with an identity block) and R^-1, both written nbp x nbp with
+// leading dimension nbp and exact zeros below the diagonal.
+//   pass 1: fail if a pivot falls below 1e-13 * max diag(G) (kappa(P)
+//           beyond about 3e6, where CholeskyQR2 loses orthogonality);
+//   pass 2: fail unless max |G - I| < 0.1 (the first pass was accurate
+//           enough for the second to reach orthogonality to rounding).
+// flag: stores the verdict if `overwrite`, else ORs into it.
+__global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const double* __restrict__ G,
+                                                      int ldg, double* __restrict__ R,
+                                                      double* __restrict__ Ri, int pass,
+                                                      int overwrite, int* flag) {
+  __shared__ Smem sm;
+  const int tid = threadIdx.x;
+  const int nbp = nt * TS;
+  if (tid == 0) sm.fail = 0;
+  double m = 0.0;
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    const double v = (i < n && j < n) ? G[i + (int64_t)j * ldg] : (i == j ? 1.0 : 0.0);
+    sm.A[i + j * LDA] = v;
+    if (i < n && j < n) {
+      if (pass == 1) {
+        if (i == j) m = fmax(m, v);
+      } else {
+        m = fmax(m, fabs(v - (i == j ? 1.0 : 0.0)));
+      }
+      if (!(v == v)) m = __builtin_inf();  // NaN input: fail below
+    }
+  }
+  __syncthreads();
+  const double gm = block_max(m, sm.red);
+  double thr;
+  if (pass == 1) {
+    if (tid == 0 && (!(gm > 0.0) || !(gm < __builtin_inf()))) sm.fail = 1;
+    thr = 1e-13 * gm;
+  } else {
+    if (tid == 0 && !(gm < 0.1)) sm.fail = 1;
+    thr = 0.5;
+  }
+  __syncthreads();
+  chol_lds(sm, n, nt, thr);
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    R[idx] = sm.A[i + j * LDA];
+  }
+  inv_upper_lds(sm, nt);
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    Ri[idx] = sm.A[i + j * LDA];
+  }
+  if (tid == 0) {
+    if (overwrite) *flag = sm.fail;
+    else if (sm.fail) *flag = 1;
+  }
+}
+
+// LU of B = QT - S (QT = top n x n block of the orthonormal factor, padded
+// with an identity block), with s_k = -sign(pivot) chosen as the pivot is
+// reached (sign(0) = +1), so |u_kk| = |pivot| + 1 >= 1.  Outputs:
+//   V(0:n, 0:n) = L1 (unit lower, explicit ones and zeros), ld ldv;
+//   Ui = U^-1, Li = L1^-1, US = U S (nbp x nbp, ld nbp); LUs: packed L\U;
+//   tau_k = -u_kk s_k;  Rout = S * RF (upper, zeros below) if Rout != NULL.
+// Flags a column whose pivot has |p| >= 1 - 2^-50: its tail below the
+// diagonal is zero, where dlarfg takes tau = 0 instead.  The one exception
+// is the last column of a square panel (square != 0), whose tail is empty:
+// there dlarfg keeps alpha (tau = 0, R(n,n) = alpha), which is s = sign(p)
+// and u = 0 here.
+__global__ __launch_bounds__(kThreads) void k_hr_lu(
+    int n, int nt, int square, const double* __restrict__ QT, int ldq, double* __restrict__ LUs,
+    double* __restrict__ Ui, double* __restrict__ Li, double* __restrict__ US,
+    const double* __restrict__ RF, int ldrf, double* __restrict__ V, int64_t ldv,
+    double* __restrict__ Rout, int64_t ldr, double* __restrict__ tau, int* flag) {
+  __shared__ Smem sm;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nbp = nt * TS;
+  if (tid == 0) sm.fail = 0;
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    sm.A[i + j * LDA] = (i < n && j < n) ? QT[i + j * ldq] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nt; ++kt) {
+    const int k0 = kt * TS;
+    double* Akk = tile(sm, kt, kt);
+    if (wave == 0) {
+      bool bad = false;
+      for (int c = 0; c < TS; ++c) {
+        const double p = Akk[c + c * LDA];
+        const bool last = square && k0 + c == n - 1;
+        double sg = p >= 0.0 ? -1.0 : 1.0;  // s = -sign(p), sign(0) = +1
+        if (last) sg = -sg;
+        if (!last && k0 + c < n && !(fabs(p) < 1.0 - 0x1p-50)) bad = true;
+        const double u = last ? 0.0 : p - sg;
+        wave_sync();
+        if (lane == 0) {
+          Akk[c + c * LDA] = u;
+          sm.sgn[k0 + c] = sg;
+        }
+        if (lane > c && lane < TS && !last) Akk[lane + c * LDA] /= u;  // L(lane, c)
+        wave_sync();
+        for (int e = lane; e < TS * TS; e += 64) {
+          const int i = e & 15, j = e >> 4;
+          if (i > c && j > c) Akk[i + j * LDA] -= Akk[i + c * LDA] * Akk[c + j * LDA];
+        }
+        wave_sync();
+      }
+      tile_inv_unit_lower(Akk, LDA, sm.D, 17);  // L_kk^-1
+      wave_sync();
+      // U_kk^-1 from the upper part of the packed tile (u = 0 only for the
+      // last column of a square panel, whose inverse is never used)
+      tile_inv_upper(Akk, LDA, sm.D2, 17);
+      if (bad && lane == 0) sm.fail = 1;
+    }
+    __syncthreads();
+    // U(kt, jt) = L_kk^-1 A(kt, jt); L(it, kt) = A(it, kt) U_kk^-1
+    const int nr = nt - 1 - kt;
+    for (int t = wave; t < 2 * nr; t += kWaves) {
+      if (t < nr) {
+        double* At = tile(sm, kt, kt + 1 + t);
+        const v4d acc = tile_mma<false, false>(vzero(), sm.D, 17, At, LDA);
+        tile_store(At, LDA, acc);
+      } else {
+        double* At = tile(sm, kt + 1 + (t - nr), kt);
+        const v4d acc = tile_mma<false, false>(vzero(), At, LDA, sm.D2, 17);
+        tile_store(At, LDA, acc);
+      }
+    }
+    __syncthreads();
+    // trailing A(it, jt) -= L(it, kt) U(kt, jt)
+    for (int t = wave; t < nr * nr; t += kWaves) {
+      const int it = kt + 1 + t % nr, jt = kt + 1 + t / nr;
+      double* At = tile(sm, it, jt);
+      v4d acc = tile_load(At, LDA);
+      const v4d p = tile_mma<false, false>(vzero(), tile(sm, it, kt), LDA, tile(sm, kt, jt), LDA);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] -= p[r];
+      tile_store(At, LDA, acc);
+    }
+    __syncthreads();
+  }
+  // Outputs from the packed L\U.
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    const double a = sm.A[i + j * LDA];
+    LUs[idx] = a;
+    US[idx] = i <= j ? a * sm.sgn[j] : 0.0;
+    if (i < n && j < n) {
+      V[i + (int64_t)j * ldv] = i > j ? a : (i == j ? 1.0 : 0.0);
+      if (Rout) Rout[i + (int64_t)j * ldr] = i <= j ? sm.sgn[i] * RF[i + (int64_t)j * ldrf] : 0.0;
+      if (i == j) tau[j] = -a * sm.sgn[j];
+    }
+  }
+  __syncthreads();
+  // U^-1 (square panels: the last diagonal entry is 0 and U^-1 is unused)
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    if (i > j) sm.A[i + j * LDA] = 0.0;
+  }
+  __syncthreads();
+  if (!square) inv_upper_lds(sm, nt);
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    Ui[idx] = sm.A[i + j * LDA];
+  }
+  __syncthreads();
+  // L1^-1
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    sm.A[i + j * LDA] = i > j ? LUs[idx] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  inv_unit_lower_lds(sm, nt);
+  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    Li[idx] = sm.A[i + j * LDA];
+  }
+  if (tid == 0 && sm.fail) *flag = 1;
+}
+
+// Writes R (upper) and the reflector tails (below) back into the dgeqrf
+// layout of P, for callers that want LAPACK's packed form.
+__global__ void k_pack_qr(int Mp, int nb, const double* __restrict__ V, int64_t ldv,
+                          const double* __restrict__ R, int64_t ldr, double* __restrict__ P,
+                          int64_t ldp) {
+  const int64_t total = (int64_t)Mp * nb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % Mp);
+    const int j = (int)(idx / Mp);
+    P[i + (int64_t)j * ldp] = i <= j ? R[i + (int64_t)j * ldr] : V[i + (int64_t)j * ldv];
+  }
+}
+
+}  // namespace
+
+size_t hr_work_bytes(int64_t Mp_max, int nb_max) {
+  (void)nb_max;
+  return (size_t)(13 * kBlk * kBlk + 2 * Mp_max * (int64_t)kBlk) * sizeof(double) + 256;
+}
+
+void hr_work_carve(void* base, int64_t Mp_max, int nb_max, HrWork* w) {
+  (void)nb_max;
+  double* p = (double*)base;
+  double** slots[] = {&w->G,  &w->R1, &w->R1i, &w->R2, &w->R2i, &w->RF, &w->QT,
+                      &w->LU, &w->Ui, &w->Li,  &w->US, &w->Wc,  &w->Cc};
+  for (double** s : slots) {
+    *s = p;
+    p += kBlk * kBlk;
+  }
+  w->Q1 = p;
+  p += Mp_max * (int64_t)kBlk;
+  w->P2 = p;
+  p += Mp_max * (int64_t)kBlk;
+  w->flag = (int*)p;
+}
+
+namespace {
+
+// One block of n <= 128 columns: CholeskyQR2, then Householder
+// reconstruction.  P is only read.  The flag is reset when `first`.
+hipError_t hr_block(hipStream_t st, int Mp, int n, const double* P, int64_t ldp, double* V,
+                    int64_t ldv, double* Rout, int64_t ldr, double* tau, double* Tw, int64_t ldtw,
+                    const HrWork& hw, double* split, size_t se, bool first) {
+  const int nt = (n + TS - 1) / TS, nbp = nt * TS;
+  hipError_t e;
+#define HR_CHK(x)                           \
+  do {                                      \
+    if ((e = (x)) != hipSuccess) return e;  \
+  } while (0)
+  // pass 1: G = P^T P, R1 = chol(G), Q1 = P R1^-1
+  HR_CHK(gemm(st, PREC_FP64, true, false, n, n, Mp, 1.0, P, ldp, P, ldp, 0.0, hw.G, nbp, split, se));
+  hipLaunchKernelGGL(k_hr_chol, dim3(1), dim3(kThreads), 0, st, n, nt, hw.G, nbp, hw.R1, hw.R1i, 1,
+                     first ? 1 : 0, hw.flag);
+  HR_CHK(gemm(st, PREC_FP64, false, false, Mp, n, n, 1.0, P, ldp, hw.R1i, nbp, 0.0, hw.Q1, Mp,
+              split, se));
+  // pass 2: G = Q1^T Q1, R2 = chol(G); R = R2 R1; top block of Q = Q1 R2^-1
+  HR_CHK(gemm(st, PREC_FP64, true, false, n, n, Mp, 1.0, hw.Q1, Mp, hw.Q1, Mp, 0.0, hw.G, nbp,
+              split, se));
+  hipLaunchKernelGGL(k_hr_chol, dim3(1), dim3(kThreads), 0, st, n, nt, hw.G, nbp, hw.R2, hw.R2i, 2,
+                     0, hw.flag);
+  HR_CHK(gemm(st, PREC_FP64, false, false, n, n, n, 1.0, hw.R2, nbp, hw.R1, nbp, 0.0, hw.RF, nbp,
+              nullptr, 0));
+  HR_CHK(gemm(st, PREC_FP64, false, false, n, n, n, 1.0, hw.Q1, Mp, hw.R2i, nbp, 0.0, hw.QT, nbp,
+              nullptr, 0));
+  // Householder reconstruction: LU of Q(0:n,:) - S; V top block, tau, S R.
+  hipLaunchKernelGGL(k_hr_lu, dim3(1), dim3(kThreads), 0, st, n, nt, Mp == n ? 1 : 0, hw.QT, nbp,
+                     hw.LU, hw.Ui, hw.Li, hw.US, hw.RF, nbp, V, ldv, Rout, ldr, tau, hw.flag);
+  // V(n:Mp, :) = Q(n:Mp, :) U^-1 = Q1(n:Mp, :) (R2^-1 U^-1); Tw = -U S L1^-T.
+  if (Mp > n) {
+    HR_CHK(gemm(st, PREC_FP64, false, false, n, n, n, 1.0, hw.R2i, nbp, hw.Ui, nbp, 0.0, hw.R1i,
+                nbp, nullptr, 0));
+    HR_CHK(gemm(st, PREC_FP64, false, false, Mp - n, n, n, 1.0, hw.Q1 + n, Mp, hw.R1i, nbp, 0.0,
+                V + n, ldv, split, se));
+  }
+  HR_CHK(gemm(st, PREC_FP64, false, true, n, n, n, -1.0, hw.US, nbp, hw.Li, nbp, 0.0, Tw, ldtw,
+              nullptr, 0));
+#undef HR_CHK
+  return hipGetLastError();
+}
+
+hipError_t hr_panel(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, double* V,
+                    int64_t ldv, double* Rout, int64_t ldr, double* tau, double* Tw, int64_t ldtw,
+                    const HrWork& hw, double* split, size_t se) {
+  if (nb <= kBlk) return hr_block(st, Mp, nb, P, ldp, V, ldv, Rout, ldr, tau, Tw, ldtw, hw, split, se, true);
+  // Two blocks: [P1 P2], n1 = 128.  H1 = I - V1 Tw1 V1^T from the first;
+  // the second factors the trailing rows of H1^T P2 (a copy); then
+  // Tw = [Tw1, -Tw1 (V1^T V2) Tw2; 0, Tw2] and R = [R11, (H1^T P2)(0:n1,:); 0, R22].
+  const int n1 = kBlk, n2 = nb - kBlk;
+  hipError_t e;
+#define HR_CHK(x)                           \
+  do {                                      \
+    if ((e = (x)) != hipSuccess) return e;  \
+  } while (0)
+  HR_CHK(hr_block(st, Mp, n1, P, ldp, V, ldv, Rout, ldr, tau, Tw, ldtw, hw, split, se, true));
+  double* P2 = hw.P2;
+  HR_CHK(copy_matrix(st, Mp, n2, P + (int64_t)n1 * ldp, ldp, P2, Mp));
+  HR_CHK(gemm(st, PREC_FP64, true, false, n1, n2, Mp, 1.0, V, ldv, P2, Mp, 0.0, hw.Wc, kBlk, split, se));
+  HR_CHK(gemm(st, PREC_FP64, true, false, n1, n2, n1, 1.0, Tw, ldtw, hw.Wc, kBlk, 0.0, hw.Cc, kBlk,
+              nullptr, 0));
+  HR_CHK(gemm(st, PREC_FP64, false, false, Mp, n2, n1, -1.0, V, ldv, hw.Cc, kBlk, 1.0, P2, Mp,
+              nullptr, 0));
+  double* V2 = V + n1 + (int64_t)n1 * ldv;
+  double* Tw2 = Tw + n1 + (int64_t)n1 * ldtw;
+  HR_CHK(hr_block(st, Mp - n1, n2, P2 + n1, Mp, V2, ldv, Rout ? Rout + n1 + (int64_t)n1 * ldr : nullptr,
+                  ldr, tau + n1, Tw2, ldtw, hw, split, se, false));
+  HR_CHK(set_zero(st, n1, n2, V + (int64_t)n1 * ldv, ldv));
+  if (Rout) {
+    HR_CHK(copy_matrix(st, n1, n2, P2, Mp, Rout + (int64_t)n1 * ldr, ldr));
+    HR_CHK(set_zero(st, n2, n1, Rout + n1, ldr));
+  }
+  HR_CHK(gemm(st, PREC_FP64, true, false, n1, n2, Mp - n1, 1.0, V + n1, ldv, V2, ldv, 0.0, hw.Wc,
+              kBlk, split, se));
+  HR_CHK(gemm(st, PREC_FP64, false, false, n1, n2, n1, 1.0, Tw, ldtw, hw.Wc, kBlk, 0.0, hw.Cc, kBlk,
+              nullptr, 0));
+  HR_CHK(gemm(st, PREC_FP64, false, false, n1, n2, n2, -1.0, hw.Cc, kBlk, Tw2, ldtw, 0.0,
+              Tw + (int64_t)n1 * ldtw, ldtw, nullptr, 0));
+  HR_CHK(set_zero(st, n2, n1, Tw + n1, ldtw));
+#undef HR_CHK
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t panel_qr_hr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, double* V,
+                       int64_t ldv, double* Rout, int64_t ldr, double* tau, double* Tw,
+                       int64_t ldtw, const HrWork& hw, const PanelWork& pw, double* split,
+                       size_t split_elems) {
+  if (nb <= 0) return hipSuccess;
+  if (nb > 2 * kBlk || Mp < nb) return hipErrorInvalidValue;
+  const int slot = prof_mark(st);
+  prof_suppress(1);
+  hipError_t e = hr_panel(st, Mp, nb, P, ldp, V, ldv, Rout, ldr, tau, Tw, ldtw, hw, split,
+                          split_elems);
+  // Fallback, gated on the flag: column-by-column Householder of the
+  // (untouched) panel, then its V and R.
+  if (e == hipSuccess) e = panel_qr(st, Mp, nb, P, ldp, tau, Tw, ldtw, pw, hw.flag);
+  if (e == hipSuccess) e = panel_extract(st, Mp, nb, P, ldp, V, ldv, Rout, ldr, hw.flag);
+  prof_suppress(-1);
+  prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb);
+  return e == hipSuccess ? hipGetLastError() : e;
+}
+
+hipError_t pack_qr(hipStream_t st, int Mp, int nb, const double* V, int64_t ldv,
+                   const double* R, int64_t ldr, double* P, int64_t ldp) {
+  const int64_t total = (int64_t)Mp * nb;
+  if (total == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pack_qr, dim3(blocks), dim3(256), 0, st, Mp, nb, V, ldv, R, ldr, P, ldp);
+  return hipGetLastError();
+}
+
+}  // namespace rutv

@@ -17,6 +17,7 @@ struct Rec {
 };
 
 bool g_on = false;
+int g_suppress = 0;  // > 0 inside a composite region timed as one class
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -41,8 +42,10 @@ const char* kNames[PC_COUNT] = {
 
 bool prof_on() { return g_on; }
 
+void prof_suppress(int delta) { g_suppress += delta; }
+
 int prof_mark(hipStream_t st) {
-  if (!g_on) return -1;
+  if (!g_on || g_suppress > 0) return -1;
   hipEvent_t a = take_event(), b = take_event();
   if (!a || !b) return -1;
   if (hipEventRecord(a, st) != hipSuccess) return -1;

@@ -33,8 +33,8 @@ constexpr int kMaxPanelRows = kPanelMaxWGGlobal * kPanelMaxRows;
 constexpr int kJacobiSweeps = 40;
 
 struct Layout {
-  size_t Y, Vh, Z, P, Uh, W, W2, C, C2, TwV, TwU, tauV, tauU, Rst, Ust, Vst, D, Jw, Jv, Ftmp,
-      split, nrm, ints, panel, total;
+  size_t Y, Vh, Z, Uh, W, W2, C, C2, TwV, TwU, tauV, tauU, Rst, Ust, Vst, D, Jw, Jv, Ftmp,
+      split, nrm, ints, panel, hr, total;
   size_t split_elems;
 };
 
@@ -58,7 +58,6 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
   L.Y = take(nb * d);
   L.Vh = take(nb * d);
   L.Z = take(mb * d);
-  L.P = take(mb * d);
   L.Uh = take(mb * d);
   L.W = take(mb * d);
   L.W2 = take(mb * d);
@@ -80,6 +79,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
   L.nrm = take(1040 * d);
   L.ints = take((2 * s + s * kJacobiSweeps + 8) * sizeof(int));
   L.panel = take(panel_work_bytes((int)b));
+  L.hr = take(hr_work_bytes(std::max(m, n), (int)b));
   L.total = off;
   return L;
 }
@@ -163,7 +163,7 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   hipStream_t st = (hipStream_t)stream;
   char* base = (char*)work;
   auto dp = [&](size_t off) { return (double*)(base + off); };
-  double *Y = dp(L.Y), *Vh = dp(L.Vh), *Z = dp(L.Z), *P = dp(L.P), *Uh = dp(L.Uh), *W = dp(L.W),
+  double *Y = dp(L.Y), *Vh = dp(L.Vh), *Z = dp(L.Z), *Uh = dp(L.Uh), *W = dp(L.W),
          *W2 = dp(L.W2), *C = dp(L.C), *C2 = dp(L.C2), *TwV = dp(L.TwV), *TwU = dp(L.TwU),
          *tauV = dp(L.tauV), *tauU = dp(L.tauU), *Rst = dp(L.Rst), *Ust = dp(L.Ust),
          *Vst = dp(L.Vst), *Dd = dp(L.D), *Jw = dp(L.Jw), *Jv = dp(L.Jv), *Ftmp = dp(L.Ftmp),
@@ -174,6 +174,8 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   int* jstatus = ints + s;
   PanelWork pw;
   panel_work_carve(base + L.panel, (int)b, &pw);
+  HrWork hw;
+  hr_work_carve(base + L.hr, std::max(m, n), (int)b, &hw);
   // Arithmetic of the sampling products (ps) and of the trailing updates (pu).
   const Prec ps = prec == kPrecMixed ? PREC_BF16X3 : (Prec)prec;
   const Prec pu = prec == kPrecMixed ? PREC_FP32 : (Prec)prec;
@@ -208,8 +210,7 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
         HIPCHK(gemm(st, ps, true, false, Ni, B, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
       }
       // [Vq, ~] = qr(Y)
-      HIPCHK(panel_qr(st, Ni, B, Y, N, tauV, TwV, B, pw));
-      HIPCHK(panel_extract(st, Ni, B, Y, N, Vh, N, nullptr, 0));
+      HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, nullptr, 0, tauV, TwV, B, hw, pw, split, se));
       // T(:, J) = T(:, J) Vq, all m rows.
       double* TJ = T + (int64_t)r0 * ldt;
       HIPCHK(gemm(st, pu, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
@@ -222,9 +223,9 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
         HIPCHK(gemm(st, PREC_FP64, false, true, N, Ni, B, -1.0, W2, M, Vh, N, 1.0, VJ, ldv, nullptr, 0));
       }
       // [Uq, R] = qr(T([I2,I3], J2))
-      HIPCHK(copy_matrix(st, Mi, B, X, ldt, P, M));
-      HIPCHK(panel_qr(st, Mi, B, P, M, tauU, TwU, B, pw));
-      HIPCHK(panel_extract(st, Mi, B, P, M, Uh, M, Rst + (size_t)i * B * B, B));
+      // (The panel is read in place; T([I2,I3], J2) is overwritten below.)
+      HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, M, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
+                         pw, split, se));
       // T([I2,I3], J3) = Uq^T T([I2,I3], J3)
       const int Nr = Ni - B;
       double* XJ3 = X + (int64_t)B * ldt;
@@ -257,9 +258,8 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
     } else {
       // Last block: economic SVD via Householder QR of T([I2,I3],[J2,J3]).
       const int c = Ni;
-      HIPCHK(copy_matrix(st, Mi, c, X, ldt, P, M));
-      HIPCHK(panel_qr(st, Mi, c, P, M, tauU, TwU, B, pw));
-      HIPCHK(panel_extract(st, Mi, c, P, M, Uh, M, Rst + (size_t)i * B * B, B));
+      HIPCHK(panel_qr_hr(st, Mi, c, X, ldt, Uh, M, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
+                         pw, split, se));
       if (formU) {
         double* UI = U + (int64_t)r0 * ldu;
         HIPCHK(gemm(st, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, W, M, split, se));
@@ -341,29 +341,48 @@ int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, doub
   return e == hipSuccess ? 0 : RANDUTV_E_HIP - (int)e;
 }
 
-size_t randutv_panel_work_size(int64_t nb) {
-  return nb < 1 || nb > kMaxB ? 0 : panel_work_bytes((int)nb);
+size_t randutv_panel_work_size(int64_t Mp, int64_t nb) {
+  if (nb < 1 || nb > kMaxB || Mp < nb || Mp > kMaxPanelRows) return 0;
+  return al256(panel_work_bytes((int)nb)) + al256(hr_work_bytes(Mp, (int)nb)) +
+         al256((size_t)Mp * nb * sizeof(double)) + al256((size_t)nb * nb * sizeof(double)) +
+         al256((size_t)kMaxSplitKSmall * nb * nb * sizeof(double));
 }
 
 int randutv_panel_qr(int64_t Mp, int64_t nb, double* P, int64_t ldp, double* tau, double* Tw,
-                     int64_t ldtw, void* work, size_t work_bytes, void* stream) {
+                     int64_t ldtw, int* used_fallback, void* work, size_t work_bytes,
+                     void* stream) {
   if (Mp < 1 || Mp > kMaxPanelRows) return -1;
   if (nb < 1 || nb > kMaxB || nb > Mp) return -2;
   if (!P || ldp < Mp) return -3;
   if (!tau) return -5;
   if (!Tw || ldtw < nb) return -6;
-  if (!work || ((uintptr_t)work & 255) || work_bytes < panel_work_bytes((int)nb)) return -8;
+  if (!work || ((uintptr_t)work & 255) || work_bytes < randutv_panel_work_size(Mp, nb))
+    return -9;
+  char* base = (char*)work;
   PanelWork pw;
-  panel_work_carve(work, (int)nb, &pw);
+  panel_work_carve(base, (int)nb, &pw);
+  base += al256(panel_work_bytes((int)nb));
+  HrWork hw;
+  hr_work_carve(base, Mp, (int)nb, &hw);
+  base += al256(hr_work_bytes(Mp, (int)nb));
+  double* V = (double*)base;
+  base += al256((size_t)Mp * nb * sizeof(double));
+  double* R = (double*)base;
+  base += al256((size_t)nb * nb * sizeof(double));
+  double* split = (double*)base;
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pw.err);
-  hipError_t e = panel_qr(st, (int)Mp, (int)nb, P, ldp, tau, Tw, ldtw, pw);
+  hipError_t e = panel_qr_hr(st, (int)Mp, (int)nb, P, ldp, V, Mp, R, nb, tau, Tw, ldtw, hw, pw,
+                             split, (size_t)kMaxSplitKSmall * nb * nb);
+  if (e == hipSuccess) e = pack_qr(st, (int)Mp, (int)nb, V, Mp, R, nb, P, ldp);
   if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
-  int err = 0;
+  int err = 0, fb = 0;
   e = hipMemcpy(&err, pw.err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&fb, hw.flag, sizeof(int), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
+  if (used_fallback) *used_fallback = fb;
   return err ? RANDUTV_E_SYNC : 0;
 }
 

@@ -102,7 +102,10 @@ def test_gemm_and_panel_validation(lib):
     assert lib.randutv_gemm(0, 0, 0, 4, 4, 4, 1.0, f, 3, f, 4, 0.0, f, 4, vp(0), 0, vp(0)) == -8
     assert lib.randutv_gemm(0, 1, 0, 4, 4, 5, 1.0, f, 4, f, 5, 0.0, f, 4, vp(0), 0, vp(0)) == -8
     assert lib.randutv_gemm(0, 0, 0, 4, 4, 4, 1.0, f, 4, f, 4, 0.0, f, 3, vp(0), 0, vp(0)) == -13
-    assert lib.randutv_panel_qr(10, 20, f, 10, f, f, 20, f, 1 << 30, vp(0)) == -2
-    assert lib.randutv_panel_qr(100, 300, f, 100, f, f, 300, f, 1 << 30, vp(0)) == -2
-    assert lib.randutv_panel_qr(100, 8, f, 99, f, f, 8, f, 1 << 30, vp(0)) == -3
-    assert lib.randutv_panel_work_size(0) == 0
+    assert lib.randutv_panel_qr(10, 20, f, 10, f, f, 20, None, f, 1 << 30, vp(0)) == -2
+    assert lib.randutv_panel_qr(100, 300, f, 100, f, f, 300, None, f, 1 << 30, vp(0)) == -2
+    assert lib.randutv_panel_qr(100, 8, f, 99, f, f, 8, None, f, 1 << 30, vp(0)) == -3
+    assert lib.randutv_panel_qr(100, 8, f, 100, f, f, 8, None, f, 16, vp(0)) == -9
+    assert lib.randutv_panel_work_size(100, 0) == 0
+    assert lib.randutv_panel_work_size(10, 20) == 0
+    assert lib.randutv_panel_work_size(8000, 256) > 8000 * 256 * 8

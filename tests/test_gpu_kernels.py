@@ -112,8 +112,10 @@ def test_panel_qr_matches_lapack(B, Mp, nb):
     dP = B.colmajor(A)
     dtau = torch.zeros(nb, dtype=torch.float64, device="cuda")
     dTw = B.colmajor(np.full((nb, nb), np.nan))
-    B.randutv_panel_qr(dP, dtau, dTw)
+    fallback = B.randutv_panel_qr(dP, dtau, dTw)
     torch.cuda.synchronize()
+    # kappa <= ~1e6 here: the CholeskyQR2 + reconstruction path must take it
+    assert not fallback
     P, tau, Tw = _np(dP), _np(dtau), _np(dTw)
     nA = np.linalg.norm(A)
     np.testing.assert_allclose(np.triu(P[:nb]), np.triu(qr[:nb]), rtol=0, atol=1e-13 * nA)
@@ -142,7 +144,7 @@ def test_panel_qr_zero_and_rank_deficient(B):
     dP = B.colmajor(A)
     dtau = torch.zeros(nb, dtype=torch.float64, device="cuda")
     dTw = B.colmajor(np.zeros((nb, nb)))
-    B.randutv_panel_qr(dP, dtau, dTw)
+    assert B.randutv_panel_qr(dP, dtau, dTw)  # rank deficient: column-by-column path
     torch.cuda.synchronize()
     tau = _np(dtau)
     assert tau[0] == 0.0 and _np(dP)[0, 0] == -2.0
@@ -207,7 +209,7 @@ def _panel_quality(B, P0):
     dP = B.colmajor(P0)
     dtau = torch.zeros(nb, dtype=torch.float64, device="cuda")
     dTw = B.colmajor(np.zeros((nb, nb)))
-    B.randutv_panel_qr(dP, dtau, dTw)
+    fallback = B.randutv_panel_qr(dP, dtau, dTw)
     torch.cuda.synchronize()
     P, T = _np(dP), _np(dTw)
     V = np.tril(P, -1)[:, :nb] + np.eye(Mp, nb)
@@ -217,10 +219,11 @@ def _panel_quality(B, P0):
     orth = np.abs(HX.T @ HX - X.T @ X).max() / np.abs(X.T @ X).max()
     Q = np.eye(Mp, nb) - V @ (T @ V[:nb].T)
     res = np.linalg.norm(P0 - Q @ R) / np.linalg.norm(P0)
-    return orth, res
+    return orth, res, fallback
 
 
-@pytest.mark.parametrize("case", ["sampling_c2", "zero_col", "tiny_block", "graded", "near_dup"])
+@pytest.mark.parametrize("case", ["sampling_c2", "zero_col", "tiny_block", "graded", "near_dup",
+                                  "sampling_c3", "gaussian", "scaled_1e150"])
 def test_panel_qr_backward_stable_on_hard_panels(B, case):
     """Householder QR is backward stable whatever the conditioning (Section 2.4
     eq. unpivQR): on graded / rank-deficient / nearly dependent panels the
@@ -233,6 +236,17 @@ def test_panel_qr_backward_stable_on_hard_panels(B, case):
         A, _ = wl.config_matrix("c2_4000")
         G = wl.gaussian_g(4000, 4000, 128, seed=1)
         P0 = A.T @ (A @ (A.T @ G[:, :128]))
+    elif case == "sampling_c3":
+        # sampling matrix of a 3000 x 3000, sigma_j = exp(-j/800) matrix (the
+        # 8000 x 8000 workload's decay), b = 256, q = 1: well conditioned
+        sig = np.exp(-np.arange(1, 3001) / 800.0) + 1e-10
+        A = wl.planted(3000, 3000, sig, seed=0)
+        G = wl.gaussian_g(3000, 3000, 256, seed=1)
+        P0 = A.T @ (A @ (A.T @ G[:, :256]))
+    elif case == "gaussian":
+        P0 = rng.standard_normal((5000, 200))
+    elif case == "scaled_1e150":
+        P0 = 1e150 * rng.standard_normal((2000, 64))
     else:
         P0 = rng.standard_normal((3000, 128))
         if case == "zero_col":
@@ -243,5 +257,8 @@ def test_panel_qr_backward_stable_on_hard_panels(B, case):
             P0 *= np.exp(-np.arange(128) / 4.0)
         else:
             P0[:, 40] = 3 * P0[:, 39] + 1e-12 * rng.standard_normal(3000)
-    orth, res = _panel_quality(B, P0)
+    orth, res, fallback = _panel_quality(B, P0)
+    print(f"panel {case}: orth {orth:.2e} res {res:.2e} fallback {fallback}", flush=True)
     assert orth < 1e-14 and res < 1e-14, (orth, res)
+    # kappa > ~3e6 must go column by column; well-conditioned panels must not
+    assert fallback == (case not in ("sampling_c3", "gaussian", "scaled_1e150"))
