@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/randutv.h"
@@ -33,8 +34,8 @@ constexpr int kMaxPanelRows = kPanelMaxWGGlobal * kPanelMaxRows;
 constexpr int kJacobiSweeps = 40;
 
 struct Layout {
-  size_t Y, Vh, Z, Uh, W, W2, C, C2, TwV, TwU, tauV, tauU, Rst, Ust, Vst, D, Jw, Jv, Ftmp,
-      split, nrm, ints, panel, hr, total;
+  size_t Y, Vh, Vh2, Z, Uh, Uh2, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwU, TwU2, tauV, tauU, Rst,
+      Ust, Vst, D, Jw, Jv, Ftmp, split, nrm, ints, panel, hr, total;
   size_t split_elems;
 };
 
@@ -57,14 +58,20 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
   };
   L.Y = take(nb * d);
   L.Vh = take(nb * d);
+  L.Vh2 = take(nb * d);
   L.Z = take(mb * d);
   L.Uh = take(mb * d);
+  L.Uh2 = take(mb * d);
   L.W = take(mb * d);
   L.W2 = take(mb * d);
+  L.Ws = take(mb * d);
+  L.W2s = take(mb * d);
   L.C = take(nb * d);
   L.C2 = take(nb * d);
   L.TwV = take(bb * d);
+  L.TwV2 = take(bb * d);
   L.TwU = take(bb * d);
+  L.TwU2 = take(bb * d);
   L.tauV = take(b * d);
   L.tauU = take(b * d);
   L.Rst = take(s * bb * d);
@@ -82,6 +89,40 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
   L.hr = take(hr_work_bytes(std::max(m, n), (int)b));
   L.total = off;
   return L;
+}
+
+// U and V accumulation runs on a second stream of the device (default
+// priority), ordered against the main stream by events: the panels and
+// small products of the main chain are latency-bound and leave most of the
+// chip idle, which the FP64 U / V block-reflector products fill.  Step i
+// uses reflector slot i % 2; the main stream waits for the side stream to
+// release a slot before overwriting it.
+struct SideCtx {
+  hipStream_t side = nullptr;
+  hipEvent_t ev[9] = {};  // V ready[2], U ready[2], V done[2], U done[2], join
+  bool ok = false;
+};
+constexpr int kMaxDevices = 64;
+SideCtx g_side[kMaxDevices];
+std::mutex g_mu;  // one factorization enqueues at a time (shared events)
+
+SideCtx* side_ctx() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  SideCtx& c = g_side[dev];
+  if (!c.ok) {
+    if (!c.side && hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) {
+      c.side = nullptr;
+      return nullptr;
+    }
+    for (auto& e : c.ev)
+      if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        e = nullptr;
+        return nullptr;
+      }
+    c.ok = true;
+  }
+  return &c;
 }
 
 __global__ void k_set_ints(int* p, int count, int v, int last) {
@@ -161,10 +202,11 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   if (work_bytes < L.total) return RANDUTV_E_WORKSPACE;
 
   hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(g_mu);
   char* base = (char*)work;
   auto dp = [&](size_t off) { return (double*)(base + off); };
-  double *Y = dp(L.Y), *Vh = dp(L.Vh), *Z = dp(L.Z), *Uh = dp(L.Uh), *W = dp(L.W),
-         *W2 = dp(L.W2), *C = dp(L.C), *C2 = dp(L.C2), *TwV = dp(L.TwV), *TwU = dp(L.TwU),
+  double *Y = dp(L.Y), *Z = dp(L.Z), *W = dp(L.W), *W2 = dp(L.W2), *Ws = dp(L.Ws),
+         *W2s = dp(L.W2s), *C = dp(L.C), *C2 = dp(L.C2),
          *tauV = dp(L.tauV), *tauU = dp(L.tauU), *Rst = dp(L.Rst), *Ust = dp(L.Ust),
          *Vst = dp(L.Vst), *Dd = dp(L.D), *Jw = dp(L.Jw), *Jv = dp(L.Jv), *Ftmp = dp(L.Ftmp),
          *split = dp(L.split), *nrm = dp(L.nrm);
@@ -182,9 +224,35 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   const size_t se = L.split_elems;
   const int M = (int)m, N = (int)n, B = (int)b;
 
+  double* const VhS[2] = {dp(L.Vh), dp(L.Vh2)};
+  double* const UhS[2] = {dp(L.Uh), dp(L.Uh2)};
+  double* const TwVS[2] = {dp(L.TwV), dp(L.TwV2)};
+  double* const TwUS[2] = {dp(L.TwU), dp(L.TwU2)};
+
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pw.err);
   if (formU) HIPCHK(set_identity(st, M, M, U, ldu));
   if (formV) HIPCHK(set_identity(st, N, N, V, ldv));
+  SideCtx* sc = (formU || formV) ? side_ctx() : nullptr;
+  const hipStream_t ss = sc ? sc->side : st;  // U / V stream (the main one if none)
+  bool vpend[2] = {false, false}, upend[2] = {false, false};
+  if (sc) {
+    HIPCHK(hipEventRecord(sc->ev[8], st));
+    HIPCHK(hipStreamWaitEvent(ss, sc->ev[8], 0));
+  }
+  // Hand the reflectors of one side to the U / V stream and back.
+  auto to_side = [&](int ready) -> hipError_t {
+    if (!sc) return hipSuccess;
+    hipError_t e = hipEventRecord(sc->ev[ready], st);
+    return e == hipSuccess ? hipStreamWaitEvent(ss, sc->ev[ready], 0) : e;
+  };
+  auto side_done = [&](int done, bool* pend) -> hipError_t {
+    if (!sc) return hipSuccess;
+    *pend = true;
+    return hipEventRecord(sc->ev[done], ss);
+  };
+  auto reclaim = [&](int done, bool pend) -> hipError_t {
+    return sc && pend ? hipStreamWaitEvent(st, sc->ev[done], 0) : hipSuccess;
+  };
 
   double normA = 0.0;
   if (tol > 0.0) {
@@ -201,6 +269,8 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
     const int r0 = (int)(i * b);
     const int Mi = M - r0, Ni = N - r0;
     double* X = T + r0 + (int64_t)r0 * ldt;
+    const int sl = (int)(i & 1);
+    double *Vh = VhS[sl], *Uh = UhS[sl], *TwV = TwVS[sl], *TwU = TwUS[sl];
     if (r0 + B < M && r0 + B < N) {
       const double* Gi = G + (int64_t)i * b * ldg;
       // Sampling matrix Y = (X^T X)^q X^T G_i.
@@ -210,20 +280,24 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
         HIPCHK(gemm(st, ps, true, false, Ni, B, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
       }
       // [Vq, ~] = qr(Y)
+      HIPCHK(reclaim(4 + sl, vpend[sl]));
       HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, nullptr, 0, tauV, TwV, B, hw, pw, split, se));
       // T(:, J) = T(:, J) Vq, all m rows.
       double* TJ = T + (int64_t)r0 * ldt;
       HIPCHK(gemm(st, pu, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
       HIPCHK(gemm(st, PREC_FP64, false, false, M, B, B, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
       HIPCHK(gemm(st, pu, false, true, M, Ni, B, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
-      if (formV) {
+      if (formV) {  // V(:, J) = V(:, J) Vq, on the U / V stream
         double* VJ = V + (int64_t)r0 * ldv;
-        HIPCHK(gemm(st, PREC_FP64, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, W, M, split, se));
-        HIPCHK(gemm(st, PREC_FP64, false, false, N, B, B, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
-        HIPCHK(gemm(st, PREC_FP64, false, true, N, Ni, B, -1.0, W2, M, Vh, N, 1.0, VJ, ldv, nullptr, 0));
+        HIPCHK(to_side(0 + sl));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, M, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, N, B, B, 1.0, Ws, M, TwV, B, 0.0, W2s, M, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, true, N, Ni, B, -1.0, W2s, M, Vh, N, 1.0, VJ, ldv, nullptr, 0));
+        HIPCHK(side_done(4 + sl, &vpend[sl]));
       }
       // [Uq, R] = qr(T([I2,I3], J2))
       // (The panel is read in place; T([I2,I3], J2) is overwritten below.)
+      HIPCHK(reclaim(6 + sl, upend[sl]));
       HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, M, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
                          pw, split, se));
       // T([I2,I3], J3) = Uq^T T([I2,I3], J3)
@@ -233,11 +307,13 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
       HIPCHK(gemm(st, PREC_FP64, true, false, B, Nr, B, 1.0, TwU, B, C, B, 0.0, C2, B, nullptr, 0));
       HIPCHK(gemm(st, pu, false, false, Mi, Nr, B, -1.0, Uh, M, C2, B, 1.0, XJ3, ldt, nullptr, 0));
       // U(:, [I2,I3]) = U(:, [I2,I3]) Uq
-      if (formU) {
+      if (formU) {  // on the U / V stream
         double* UI = U + (int64_t)r0 * ldu;
-        HIPCHK(gemm(st, PREC_FP64, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, W, M, split, se));
-        HIPCHK(gemm(st, PREC_FP64, false, false, M, B, B, 1.0, W, M, TwU, B, 0.0, W2, M, nullptr, 0));
-        HIPCHK(gemm(st, PREC_FP64, false, true, M, Mi, B, -1.0, W2, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+        HIPCHK(to_side(2 + sl));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, M, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, M, B, B, 1.0, Ws, M, TwU, B, 0.0, W2s, M, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, true, M, Mi, B, -1.0, W2s, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+        HIPCHK(side_done(6 + sl, &upend[sl]));
       }
       // T([I2,I3], J2) = [R; 0]; R moves to the stash, the diagonal block is
       // written from the SVD after the loop.
@@ -258,13 +334,16 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
     } else {
       // Last block: economic SVD via Householder QR of T([I2,I3],[J2,J3]).
       const int c = Ni;
+      HIPCHK(reclaim(6 + sl, upend[sl]));
       HIPCHK(panel_qr_hr(st, Mi, c, X, ldt, Uh, M, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
                          pw, split, se));
       if (formU) {
         double* UI = U + (int64_t)r0 * ldu;
-        HIPCHK(gemm(st, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, W, M, split, se));
-        HIPCHK(gemm(st, PREC_FP64, false, false, M, c, c, 1.0, W, M, TwU, B, 0.0, W2, M, nullptr, 0));
-        HIPCHK(gemm(st, PREC_FP64, false, true, M, Mi, c, -1.0, W2, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+        HIPCHK(to_side(2 + sl));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, M, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, c, 1.0, Ws, M, TwU, B, 0.0, W2s, M, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, true, M, Mi, c, -1.0, W2s, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+        HIPCHK(side_done(6 + sl, &upend[sl]));
       }
       HIPCHK(set_zero(st, Mi, c, X, ldt));
       widths.push_back(c);
@@ -272,6 +351,10 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
     }
   }
 
+  if (sc) {  // join the U / V stream
+    HIPCHK(hipEventRecord(sc->ev[8], ss));
+    HIPCHK(hipStreamWaitEvent(st, sc->ev[8], 0));
+  }
   // Batched SVDs of the stashed R blocks, then fold the rotations back:
   // T(I2,J2) = Ds, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) = T(I1,J2) Vs,
   // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.
