@@ -127,6 +127,37 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q,
 
 /* ---- Building blocks of one step (exported for testing and reuse) ---- */
 
+/* Truncated approximation (Section 6.2, eq. Ak_randUTV; Theorem of Section
+ * 5.3): A_k = U_k U_k^T A, with U_k the first k columns of U after t = k / b
+ * steps of randUTV on A (m x n, m >= n, m <= 32768), b <= 128, k a multiple
+ * of b with 0 < k < n.  The b x b SVDs are skipped: U_k U_k^T does not depend
+ * on them.  A (lda), G (packed Gaussian as for randutv_factor, ldg) are read;
+ * Uk (m x k, lduk) and, unless Ak == NULL, Ak (m x n, ldak) are written;
+ * `tape` (randutv_approx_tape_size bytes, device) receives the reflectors
+ * and R factors of the t steps for randutv_approx_backward.  prec as for
+ * randutv_factor (argument 16).  work: randutv_approx_work_size bytes,
+ * 256-byte aligned.  Enqueued on `stream`; returns without waiting. */
+size_t randutv_approx_tape_size(int64_t m, int64_t n, int64_t b, int64_t k);
+size_t randutv_approx_work_size(int64_t m, int64_t n, int64_t b, int q, int64_t k);
+int randutv_approx(int64_t m, int64_t n, int64_t b, int q, int64_t k, const double* A,
+                   int64_t lda, const double* G, int64_t ldg, double* Ak, int64_t ldak,
+                   double* Uk, int64_t lduk, double* tape, size_t tape_bytes, int prec,
+                   void* work, size_t work_bytes, void* stream);
+
+/* Reverse-mode derivative of A -> A_k with G held fixed: Abar (m x n, ldab)
+ * = J^T Akbar, from A, G, the Uk and tape written by randutv_approx on the
+ * same arguments (the trailing matrices of every step are recomputed from A
+ * and the tape; no dense U or V is stored).  Defined wherever no Householder
+ * sign decision of the t steps flips (where A_k is smooth).  prec is
+ * argument 18; work: randutv_approx_backward_work_size bytes, 256-byte
+ * aligned.  Enqueued on `stream`. */
+size_t randutv_approx_backward_work_size(int64_t m, int64_t n, int64_t b, int q, int64_t k);
+int randutv_approx_backward(int64_t m, int64_t n, int64_t b, int q, int64_t k, const double* A,
+                            int64_t lda, const double* G, int64_t ldg, const double* Uk,
+                            int64_t lduk, const double* tape, size_t tape_bytes,
+                            const double* Akbar, int64_t ldakb, double* Abar, int64_t ldab,
+                            int prec, void* work, size_t work_bytes, void* stream);
+
 /* Thin-matrix product of the sampling and update stages (Section 1.1 (iii);
  * Section 5.4): C = alpha * op(A) * op(B) + beta * C, all FP64 column-major in
  * memory, op(X) = X^T when tX != 0, inner products in `prec` arithmetic.

@@ -68,6 +68,18 @@ def lib():
     L.randutv_profile_end.restype = i32
     L.randutv_profile_class_name.argtypes = [i32]
     L.randutv_profile_class_name.restype = ctypes.c_char_p
+    L.randutv_approx_tape_size.argtypes = [i64, i64, i64, i64]
+    L.randutv_approx_tape_size.restype = sz
+    L.randutv_approx_work_size.argtypes = [i64, i64, i64, i32, i64]
+    L.randutv_approx_work_size.restype = sz
+    L.randutv_approx_backward_work_size.argtypes = [i64, i64, i64, i32, i64]
+    L.randutv_approx_backward_work_size.restype = sz
+    L.randutv_approx.argtypes = [i64, i64, i64, i32, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                 vp, sz, i32, vp, sz, vp]
+    L.randutv_approx.restype = i32
+    L.randutv_approx_backward.argtypes = [i64, i64, i64, i32, i64, vp, i64, vp, i64, vp, i64, vp,
+                                          sz, vp, i64, vp, i64, i32, vp, sz, vp]
+    L.randutv_approx_backward.restype = i32
     L.randutv_strerror.argtypes = [i32]
     L.randutv_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -77,7 +89,9 @@ def lib():
 EXPORTS = ["randutv_random_steps", "randutv_g_cols", "randutv_workspace_size",
            "randutv_factor", "randutv_gemm", "randutv_panel_work_size", "randutv_panel_qr",
            "randutv_small_svd_work_size", "randutv_small_svd", "randutv_strerror",
-           "randutv_profile_begin", "randutv_profile_end", "randutv_profile_class_name"]
+           "randutv_profile_begin", "randutv_profile_end", "randutv_profile_class_name",
+           "randutv_approx_tape_size", "randutv_approx_work_size", "randutv_approx",
+           "randutv_approx_backward_work_size", "randutv_approx_backward"]
 
 
 def profile_begin():
@@ -236,3 +250,41 @@ def randutv_small_svd(R, nbs):
     if st not in (0, 1):
         _check(st, "randutv_small_svd")
     return Us, D, Vs, st
+
+
+def randutv_approx(A, G, b, q, k, prec="fp64", want_ak=True):
+    """Truncated approximation through the C ABI.  A, G: FP64 column-major
+    device tensors.  Returns (Ak or None, Uk, tape)."""
+    m, n = A.shape
+    tb = int(lib().randutv_approx_tape_size(m, n, b, k))
+    wb = int(lib().randutv_approx_work_size(m, n, b, q, k))
+    if tb == 0 or wb == 0:
+        raise RandUTVError(f"randutv_approx: unsupported shape m={m} n={n} b={b} q={q} k={k}")
+    tape = torch.empty(tb // 8, dtype=torch.float64, device=A.device)
+    ws = workspace(wb, A.device)
+    wp, wbytes = _aligned_ptr(ws)
+    Uk = empty_colmajor(m, k, A.device)
+    Ak = empty_colmajor(m, n, A.device) if want_ak else None
+    _check(lib().randutv_approx(m, n, b, q, k, _ptr(A), _ld(A, m), _ptr(G), _ld(G, m),
+                                _ptr(Ak) if Ak is not None else None,
+                                _ld(Ak, m) if Ak is not None else m, _ptr(Uk), _ld(Uk, m),
+                                _ptr(tape), tb, PREC[prec], wp, wbytes, _stream()),
+           "randutv_approx")
+    return Ak, Uk, tape
+
+
+def randutv_approx_backward(A, G, b, q, k, Uk, tape, Akbar, prec="fp64"):
+    """Abar = J^T Akbar for A -> A_k (G fixed), through the C ABI."""
+    m, n = A.shape
+    wb = int(lib().randutv_approx_backward_work_size(m, n, b, q, k))
+    if wb == 0:
+        raise RandUTVError("randutv_approx_backward: unsupported shape")
+    ws = workspace(wb, A.device)
+    wp, wbytes = _aligned_ptr(ws)
+    Abar = empty_colmajor(m, n, A.device)
+    _check(lib().randutv_approx_backward(m, n, b, q, k, _ptr(A), _ld(A, m), _ptr(G), _ld(G, m),
+                                         _ptr(Uk), _ld(Uk, m), _ptr(tape), tape.numel() * 8,
+                                         _ptr(Akbar), _ld(Akbar, m), _ptr(Abar), _ld(Abar, m),
+                                         PREC[prec], wp, wbytes, _stream()),
+           "randutv_approx_backward")
+    return Abar

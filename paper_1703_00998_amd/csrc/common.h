@@ -98,6 +98,10 @@ hipError_t panel_qr_hr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, d
                        int64_t ldv, double* Rout, int64_t ldr, double* tau, double* Tw,
                        int64_t ldtw, const HrWork& hw, const PanelWork& pw, double* split,
                        size_t split_elems);
+// Xi = X^-1 for X (n x n, n <= 128) upper triangular, or unit lower
+// triangular when !upper (diagonal taken as 1); zeros outside the triangle.
+hipError_t tri_inv(hipStream_t st, int n, const double* X, int64_t ldx, double* Xi, int64_t ldxi,
+                   bool upper);
 // P = [R above and on the diagonal; V below] (LAPACK dgeqrf layout).
 hipError_t pack_qr(hipStream_t st, int Mp, int nb, const double* V, int64_t ldv,
                    const double* R, int64_t ldr, double* P, int64_t ldp);
@@ -113,6 +117,32 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld,
                        const double* R, int64_t strideR, double* Us, double* Vs,
                        int64_t strideUV, double* D, int64_t strideD, double* Wk,
                        double* Vk, int* status, int max_sweeps);
+
+// ---------------------------------------------------------------- factor core
+// Reflectors and R factors of the first t steps, for the truncated
+// approximation and its backward: per step i, Vy (n x b, ld n), Ty and Ry
+// (b x b), Vu (m x b, ld m), Tu and Ru (b x b).
+struct ApproxTape {
+  double* p;
+  int64_t m, n, b, t;
+  int64_t stride() const { return n * b + m * b + 4 * b * b; }
+  double* Vy(int64_t i) const { return p + i * stride(); }
+  double* Ty(int64_t i) const { return Vy(i) + n * b; }
+  double* Ry(int64_t i) const { return Ty(i) + b * b; }
+  double* Vu(int64_t i) const { return Ry(i) + b * b; }
+  double* Tu(int64_t i) const { return Vu(i) + m * b; }
+  double* Ru(int64_t i) const { return Tu(i) + b * b; }
+  static size_t bytes(int64_t m, int64_t n, int64_t b, int64_t t) {
+    return (size_t)t * (n * b + m * b + 4 * b * b) * sizeof(double);
+  }
+};
+// randutv_factor's body; with a tape, the reflectors of every step are kept
+// there and the loop ends without the small SVDs (k_stop must be set).
+int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, const double* G,
+                int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv, int64_t k_stop,
+                double tol, int prec, unsigned flags, void* work, size_t work_bytes,
+                int64_t* k_out, void* stream, const ApproxTape* tape);
+size_t factor_work_bytes(int64_t m, int64_t n, int64_t b);
 
 // ---------------------------------------------------------------- misc
 hipError_t copy_matrix(hipStream_t st, int M, int N, const double* A, int64_t lda,

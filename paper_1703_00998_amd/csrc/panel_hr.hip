@@ -465,6 +465,29 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
   if (tid == 0 && sm.fail) *flag = 1;
 }
 
+// Inverse of an n x n (n <= 128) upper-triangular (upper != 0) or
+// unit-lower-triangular (diagonal taken as 1) matrix; entries outside the
+// triangle are ignored and written as zeros.
+__global__ __launch_bounds__(kThreads) void k_tri_inv(int n, int nt, const double* __restrict__ X,
+                                                      int64_t ldx, double* __restrict__ Xi,
+                                                      int64_t ldxi, int upper) {
+  __shared__ Smem sm;
+  const int nbp = nt * TS;
+  for (int idx = threadIdx.x; idx < nbp * nbp; idx += kThreads) {
+    const int i = idx % nbp, j = idx / nbp;
+    double v = i == j ? 1.0 : 0.0;
+    if (i < n && j < n && (upper ? i <= j : i > j)) v = X[i + (int64_t)j * ldx];
+    sm.A[i + j * LDA] = v;
+  }
+  __syncthreads();
+  if (upper) inv_upper_lds(sm, nt);
+  else inv_unit_lower_lds(sm, nt);
+  for (int idx = threadIdx.x; idx < n * n; idx += kThreads) {
+    const int i = idx % n, j = idx / n;
+    Xi[i + (int64_t)j * ldxi] = sm.A[i + j * LDA];
+  }
+}
+
 // Writes R (upper) and the reflector tails (below) back into the dgeqrf
 // layout of P, for callers that want LAPACK's packed form.
 __global__ void k_pack_qr(int Mp, int nb, const double* __restrict__ V, int64_t ldv,
@@ -606,6 +629,16 @@ hipError_t panel_qr_hr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, d
   prof_suppress(-1);
   prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb);
   return e == hipSuccess ? hipGetLastError() : e;
+}
+
+hipError_t tri_inv(hipStream_t st, int n, const double* X, int64_t ldx, double* Xi, int64_t ldxi,
+                   bool upper) {
+  if (n <= 0) return hipSuccess;
+  if (n > kBlk) return hipErrorInvalidValue;
+  const int nt = (n + TS - 1) / TS;
+  hipLaunchKernelGGL(k_tri_inv, dim3(1), dim3(kThreads), 0, st, n, nt, X, ldx, Xi, ldxi,
+                     upper ? 1 : 0);
+  return hipGetLastError();
 }
 
 hipError_t pack_qr(hipStream_t st, int Mp, int nb, const double* V, int64_t ldv,

@@ -184,6 +184,19 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
                    const double* G, int64_t ldg, double* U, int64_t ldu, double* V,
                    int64_t ldv, int64_t k_stop, double tol, int prec, unsigned flags,
                    void* work, size_t work_bytes, int64_t* k_out, void* stream) {
+  return rutv::factor_impl(m, n, b, q, T, ldt, G, ldg, U, ldu, V, ldv, k_stop, tol, prec, flags,
+                           work, work_bytes, k_out, stream, nullptr);
+}
+}  // extern "C"
+
+namespace rutv {
+
+size_t factor_work_bytes(int64_t m, int64_t n, int64_t b) { return make_layout(m, n, b).total; }
+
+int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, const double* G,
+                int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv, int64_t k_stop,
+                double tol, int prec, unsigned flags, void* work, size_t work_bytes,
+                int64_t* k_out, void* stream, const ApproxTape* tape) {
   if (m < 1 || n < 1) return -1;
   if (m < n) return RANDUTV_E_UNSUPPORTED;
   if (m > kMaxPanelRows || m * n > ((int64_t)1 << 40)) return RANDUTV_E_UNSUPPORTED;
@@ -271,6 +284,15 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
     double* X = T + r0 + (int64_t)r0 * ldt;
     const int sl = (int)(i & 1);
     double *Vh = VhS[sl], *Uh = UhS[sl], *TwV = TwVS[sl], *TwU = TwUS[sl];
+    double *RV = nullptr, *RU = Rst + (size_t)i * B * B;
+    if (tape) {  // reflectors and R factors of this step go to the tape
+      Vh = tape->Vy(i);
+      TwV = tape->Ty(i);
+      RV = tape->Ry(i);
+      Uh = tape->Vu(i);
+      TwU = tape->Tu(i);
+      RU = tape->Ru(i);
+    }
     if (r0 + B < M && r0 + B < N) {
       const double* Gi = G + (int64_t)i * b * ldg;
       // Sampling matrix Y = (X^T X)^q X^T G_i.
@@ -281,7 +303,7 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
       }
       // [Vq, ~] = qr(Y)
       HIPCHK(reclaim(4 + sl, vpend[sl]));
-      HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, nullptr, 0, tauV, TwV, B, hw, pw, split, se));
+      HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, RV, B, tauV, TwV, B, hw, pw, split, se));
       // T(:, J) = T(:, J) Vq, all m rows.
       double* TJ = T + (int64_t)r0 * ldt;
       HIPCHK(gemm(st, pu, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
@@ -298,8 +320,7 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
       // [Uq, R] = qr(T([I2,I3], J2))
       // (The panel is read in place; T([I2,I3], J2) is overwritten below.)
       HIPCHK(reclaim(6 + sl, upend[sl]));
-      HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, M, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
-                         pw, split, se));
+      HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, M, RU, B, tauU, TwU, B, hw, pw, split, se));
       // T([I2,I3], J3) = Uq^T T([I2,I3], J3)
       const int Nr = Ni - B;
       double* XJ3 = X + (int64_t)B * ldt;
@@ -355,6 +376,10 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
     HIPCHK(hipEventRecord(sc->ev[8], ss));
     HIPCHK(hipStreamWaitEvent(st, sc->ev[8], 0));
   }
+  if (tape) {  // truncated approximation: no small SVDs (U_k U_k^T does not see them)
+    if (k_out) *k_out = k_done;
+    return 0;
+  }
   // Batched SVDs of the stashed R blocks, then fold the rotations back:
   // T(I2,J2) = Ds, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) = T(I1,J2) Vs,
   // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.
@@ -404,6 +429,9 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   return 0;
 }
 
+}  // namespace rutv
+
+extern "C" {
 
 int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
