@@ -112,6 +112,81 @@ def run_path(B, torch, dA, dG, sig, m, n, b, q, prec, steps, warmup):
     return ms_step, prof, acc, d
 
 
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def early_stop_run(B, torch, wl):
+    """20000 x 5000 rank-300 + 1e-8 noise, b = 128, q = 2, tol = 1e-6: time to
+    the stopping rank (U, V not formed; the early-stop test reads one norm
+    back per step), the rank found and ||A - A_k|| / ||A||."""
+    import numpy as np
+    try:
+        A, sig = wl.config_matrix("c4_20000x5000")
+        m, n, b, q = 20000, 5000, 128, 2
+        dA = B.colmajor(A)
+        dG = B.colmajor(wl.gaussian_g(m, n, b, seed=1))
+        nA = float(np.linalg.norm(A))
+        del A
+        T = B.empty_colmajor(m, n)
+        work = B.workspace(B.workspace_size(m, n, b, q, "fp64", False, False))
+        res = {}
+
+        def step():
+            T.copy_(dA)
+            res["k"] = B.randutv_factor(T, dG, b, q, tol=1e-6, work=work)
+
+        ms = _timed(torch, step, 3)
+        k = res["k"]
+        tail = torch.linalg.norm(T[k:, k:]).item() / nA
+        log(f"early stop: k={k}, {ms:.2f} ms, ||A-A_k||/||A|| = {tail:.3e}")
+        return {"ms": ms, "k": k, "rel_err": tail,
+                "config": "20000x5000 rank-300 (sigma_j=1/j) + noise 1e-8||A||, b=128, q=2, "
+                          "tol=1e-6, FP64, U,V not formed"}
+    except Exception as e:  # reported, never fatal to the headline line
+        return {"error": repr(e)}
+
+
+def approx_run(B, torch, wl):
+    """2048 x 1024, sigma_j = exp(-j/100), b = 64, q = 1, k = 128: forward
+    A_k and the hand-written backward of L = ||A_k - B||^2, FP64 storage,
+    FP64 and FP32 products."""
+    import numpy as np
+    try:
+        m, n, b, q, k = 2048, 1024, 64, 1, 128
+        A, _ = wl.config_matrix("c5_2048x1024")
+        dA = B.colmajor(A)
+        dG = B.colmajor(wl.gaussian_g(m, n, b, seed=1))
+        Bt = B.colmajor(np.random.default_rng(3).standard_normal((m, n)))
+        out = {"config": "2048x1024, sigma_j=exp(-j/100), b=64, q=1, k=128, loss ||A_k-B||^2"}
+        for prec in ("fp64", "fp32"):
+            st = {}
+
+            def fwd():
+                st["f"] = B.randutv_approx(dA, dG, b, q, k, prec=prec)
+
+            def bwd():
+                Ak, Uk, tape = st["f"]
+                B.randutv_approx_backward(dA, dG, b, q, k, Uk, tape, 2.0 * (Ak - Bt), prec=prec)
+
+            fms = _timed(torch, fwd, 5)
+            bms = _timed(torch, bwd, 5)
+            out[prec] = {"forward_ms": fms, "backward_ms": bms}
+            log(f"approx {prec}: forward {fms:.2f} ms, backward {bms:.2f} ms")
+        return out
+    except Exception as e:
+        return {"error": repr(e)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +197,8 @@ def main():
                     help="comma list of paths from " + ",".join(PRECS) + "; the headline "
                          "value is the fastest path meeting its error bound, FP64 included")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the early-stop and differentiation workload timings")
     ap.add_argument("--cpu-n", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -203,6 +280,9 @@ def main():
         "paper_context": {"randUTV_q1_n8000_UV_formed_s": 26.4, "hardware":
                           "Xeon E5-2695 v3, 14 cores, MKL 11.2.3, b=64 (Table 1)"},
     }
+    if not args.no_extra:
+        out["early_stop_20000x5000"] = early_stop_run(B, torch, wl)
+        out["approx_2048x1024"] = approx_run(B, torch, wl)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_n}x{args.cpu_n} sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, b, q)

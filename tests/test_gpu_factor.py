@@ -207,3 +207,33 @@ def test_full_size_invariants_and_theorem(B, name):
     r2 = abs(np.linalg.norm(T1h[b:, b:]) - e2) / e2
     print(f"{name}: theorem (a) rel diff {r1:.3e}, (b) rel diff {r2:.3e}")
     assert r1 <= 1e-6 and r2 <= 1e-6
+
+
+def test_early_stop_20000x5000_workload(B):
+    """Early-stop workload (Section 1.1 (ii)): 20000 x 5000, rank-300 planted
+    (sigma_j = 1/j) plus Gaussian noise of norm 1e-8 ||A||, b = 128, q = 2,
+    tol = 1e-6: the trailing norm first falls below tol ||A|| after three
+    steps (k = 384, the first multiple of 128 above 300).  Then
+    ||A - A_k||_F = ||T(k:, k:)||_F (Theorem, Section 5.3) lies between what
+    is left of the noise and the whole noise, ||T||_F = ||A||_F, and the
+    processed columns are upper triangular with diagonal blocks."""
+    A, sig = wl.config_matrix("c4_20000x5000")
+    m, n, b, q = 20000, 5000, 128, 2
+    G = wl.gaussian_g(m, n, b, seed=1)
+    nA = np.linalg.norm(A)
+    nE = 1e-8 * np.linalg.norm(sig)  # the planted noise norm
+    print("c4 inputs ready", flush=True)
+    _, T, _, k = gpu_factor(B, A, b, q, G, form=False, tol=1e-6)
+    del G
+    assert k == 384
+    Th = _np(T)
+    tail = np.linalg.norm(Th[k:, k:])
+    print(f"c4: k={k} ||A - A_k||/||A|| = {tail / nA:.4e}", flush=True)
+    # removing k - 300 = 84 of the 5000 noise directions takes away a few
+    # percent of its energy, never more than the largest 84 of them
+    assert 0.9 * nE <= tail <= nE * (1 + 1e-6)
+    assert abs(np.linalg.norm(Th) - nA) <= 1e-12 * nA
+    assert np.all(np.tril(Th[:, :k], -1) == 0.0)
+    for s0 in range(0, k, b):
+        blk = Th[s0:s0 + b, s0:s0 + b]
+        assert np.all(blk - np.diag(np.diag(blk)) == 0.0)
