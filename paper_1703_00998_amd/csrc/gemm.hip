@@ -335,7 +335,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     launch_p<PREC_BF16X3>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else
     launch_p<PREC_FP64>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  prof_done(st, slot, 4 * (int)prec + (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN)),
+  prof_done(st, slot, 12 * (big ? 1 : 0) + 4 * (int)prec +
+                          (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN)),
             2.0 * M * N * (double)K);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;

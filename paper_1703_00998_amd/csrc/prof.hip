@@ -32,11 +32,16 @@ hipEvent_t take_event() {
   return e;
 }
 
+// Class names: gemm_<op(A)op(B)>_<arithmetic>_<tile>, e.g. gemm_nt_fp32_t128
+// is k_gemm<PREC_FP32, false, true, 128, 128>.
 const char* kNames[PC_COUNT] = {
-    "gemm_nn",        "gemm_tn",        "gemm_nt",        "gemm_tt",
-    "gemm_nn_fp32",   "gemm_tn_fp32",   "gemm_nt_fp32",   "gemm_tt_fp32",
-    "gemm_nn_bf16x3", "gemm_tn_bf16x3", "gemm_nt_bf16x3", "gemm_tt_bf16x3",
-    "splitk_reduce",  "panel_qr",       "small_svd"};
+    "gemm_nn_fp64_t64",    "gemm_tn_fp64_t64",    "gemm_nt_fp64_t64",    "gemm_tt_fp64_t64",
+    "gemm_nn_fp32_t64",    "gemm_tn_fp32_t64",    "gemm_nt_fp32_t64",    "gemm_tt_fp32_t64",
+    "gemm_nn_bf16x3_t64",  "gemm_tn_bf16x3_t64",  "gemm_nt_bf16x3_t64",  "gemm_tt_bf16x3_t64",
+    "gemm_nn_fp64_t128",   "gemm_tn_fp64_t128",   "gemm_nt_fp64_t128",   "gemm_tt_fp64_t128",
+    "gemm_nn_fp32_t128",   "gemm_tn_fp32_t128",   "gemm_nt_fp32_t128",   "gemm_tt_fp32_t128",
+    "gemm_nn_bf16x3_t128", "gemm_tn_bf16x3_t128", "gemm_nt_bf16x3_t128", "gemm_tt_bf16x3_t128",
+    "splitk_reduce",       "panel_qr",            "small_svd"};
 
 }  // namespace
 
