@@ -40,12 +40,6 @@ __device__ inline v4d mfma(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // acc += op(A) op(B) for 16 x 16 tiles (K = 16).  Tiles are column-major with
 // leading dimensions lda / ldb; TA / TB take the transpose.  MFMA operand
 // layout: A(i, k) from lane i + 16k, B(k, j) from lane j + 16k; result
@@ -91,46 +85,84 @@ __device__ inline v4d mma_reg_b(v4d acc, const double* A, int lda, v4d b) {
   return acc;
 }
 
-// Inverse of the upper-triangular 16 x 16 tile U into X (both column-major,
-// leading dimensions ldu / ldx) by one wave: lane j < 16 back-substitutes
-// column j.
-__device__ void tile_inv_upper(const double* U, int ldu, double* X, int ldx) {
-  const int l = threadIdx.x & 63;
-  if (l < TS) {
-    const int j = l;
-    double x[TS];
+// ---- 16 x 16 tiles in registers, one wave: lane j < 16 holds column j
+// (a[i] = X(i, j)); lanes 16..63 carry copies that are never stored.  Values
+// of other columns are read with readlane at compile-time lane indices.
+
+__device__ inline double rl(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ inline void col_load(const double* T, int ld, double (&a)[TS]) {
+  const int j = threadIdx.x & 15;
 #pragma unroll
-    for (int i = 0; i < TS; ++i) x[i] = 0.0;
+  for (int i = 0; i < TS; ++i) a[i] = T[i + j * ld];
+}
+
+__device__ inline void col_store(double* T, int ld, const double (&a)[TS]) {
+  const int j = threadIdx.x & 63;
+  if (j < TS) {
 #pragma unroll
-    for (int i = TS - 1; i >= 0; --i) {
-      if (i <= j) {
-        double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = i + 1; k < TS; ++k) s -= U[i + k * ldu] * x[k];
-        x[i] = s / U[i + i * ldu];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < TS; ++i) X[i + j * ldx] = x[i];
+    for (int i = 0; i < TS; ++i) T[i + j * ld] = a[i];
   }
 }
 
-// Inverse of the unit-lower-triangular 16 x 16 tile L (diagonal taken as 1,
-// whatever is stored there) into X by one wave.
-__device__ void tile_inv_unit_lower(const double* L, int ldl, double* X, int ldx) {
-  const int l = threadIdx.x & 63;
-  if (l < TS) {
-    const int j = l;
-    double x[TS];
+// Upper Cholesky of the symmetric tile in a (both triangles present): on
+// return a holds R (zeros below the diagonal).  A pivot at or below thr in a
+// real column (k0 + c < n) is replaced by 1 and reported through bad.
+__device__ inline void chol16(double (&a)[TS], int k0, int n, double thr, bool& bad) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int i = 0; i < TS; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) s -= L[i + k * ldl] * x[k];
-      x[i] = (i < j) ? 0.0 : s;
+  for (int c = 0; c < TS; ++c) {
+    double d = rl(a[c], c);
+    if (k0 + c < n && !(d > thr)) {
+      bad = true;
+      d = 1.0;
     }
+    const double r = sqrt(d), ri = 1.0 / r;
+    const double rcj = a[c] * ri;  // R(c, lane)
 #pragma unroll
-    for (int i = 0; i < TS; ++i) X[i + j * ldx] = x[i];
+    for (int i = c + 1; i < TS; ++i) {
+      const double lic = rl(a[i], c) * ri;
+      if (lane > c) a[i] -= lic * rcj;
+    }
+    if (lane >= c) a[c] = (lane == c) ? r : rcj;
+  }
+#pragma unroll
+  for (int i = 0; i < TS; ++i)
+    if (i > lane) a[i] = 0.0;
+}
+
+// x = inverse of the upper-triangular tile in a (x zero below the diagonal).
+__device__ inline void inv_upper16(const double (&a)[TS], double (&x)[TS]) {
+  const int lane = threadIdx.x & 63;
+  double myd = 1.0;
+#pragma unroll
+  for (int i = 0; i < TS; ++i)
+    if (lane == i) myd = a[i];
+  const double myinv = 1.0 / myd;
+#pragma unroll
+  for (int i = TS - 1; i >= 0; --i) {
+    double s = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = i + 1; k < TS; ++k) s -= rl(a[i], k) * x[k];
+    x[i] = s * rl(myinv, i);
+  }
+}
+
+// x = inverse of the unit-lower-triangular tile in a (strict lower part
+// used, diagonal taken as 1; x zero above the diagonal).
+__device__ inline void inv_unit_lower16(const double (&a)[TS], double (&x)[TS]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < TS; ++i) {
+    double s = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= rl(a[i], k) * x[k];
+    x[i] = s;
   }
 }
 
@@ -157,6 +189,14 @@ __device__ inline double block_max(double v, double* red) {
   return r;
 }
 
+// Element loops over an nbp x nbp matrix: thread t takes row t % nbp and
+// every (kThreads / nbp)-th column from t / nbp (consecutive threads on
+// consecutive rows; threads beyond a whole number of columns sit out).
+__device__ inline int elem_j0(int nbp) {
+  const int js = kThreads / nbp;
+  return (int)threadIdx.x < js * nbp ? (int)threadIdx.x / nbp : nbp;
+}
+
 // (a, b) with 0 <= a <= b < n from a linear index over the upper triangle.
 __device__ inline void upper_pair(int t, int n, int& a, int& b) {
   a = 0;
@@ -178,28 +218,12 @@ __device__ void chol_lds(Smem& sm, int n, int nt, double thr) {
     double* Akk = tile(sm, kt, kt);
     if (wave == 0) {
       bool bad = false;
-      for (int c = 0; c < TS; ++c) {
-        double d = Akk[c + c * LDA];
-        if (k0 + c < n && !(d > thr)) {
-          bad = true;
-          d = 1.0;
-        }
-        const double r = sqrt(d);
-        wave_sync();
-        if (lane >= c && lane < TS) Akk[c + lane * LDA] = (lane == c) ? r : Akk[c + lane * LDA] / r;
-        wave_sync();
-        for (int e = lane; e < TS * TS; e += 64) {
-          const int i = e & 15, j = e >> 4;
-          if (i > c && j >= i) Akk[i + j * LDA] -= Akk[c + i * LDA] * Akk[c + j * LDA];
-        }
-        wave_sync();
-      }
-      for (int e = lane; e < TS * TS; e += 64) {
-        const int i = e & 15, j = e >> 4;
-        if (i > j) Akk[i + j * LDA] = 0.0;
-      }
-      wave_sync();
-      tile_inv_upper(Akk, LDA, sm.D, 17);
+      double a[TS], x[TS];
+      col_load(Akk, LDA, a);
+      chol16(a, k0, n, thr, bad);
+      col_store(Akk, LDA, a);
+      inv_upper16(a, x);
+      col_store(sm.D, 17, x);
       if (bad && lane == 0) sm.fail = 1;
     }
     __syncthreads();
@@ -225,8 +249,7 @@ __device__ void chol_lds(Smem& sm, int n, int nt, double thr) {
     }
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (threadIdx.x) % nbp; j < nbp; j += kThreads / nbp) {
     if (i > j) sm.A[i + j * LDA] = 0.0;
   }
   __syncthreads();
@@ -237,7 +260,12 @@ __device__ void chol_lds(Smem& sm, int n, int nt, double thr) {
 __device__ void inv_upper_lds(Smem& sm, int nt) {
   const int wave = threadIdx.x >> 6;
   for (int it = nt - 1; it >= 0; --it) {
-    if (wave == 0) tile_inv_upper(tile(sm, it, it), LDA, sm.D, 17);
+    if (wave == 0) {
+      double a[TS], x[TS];
+      col_load(tile(sm, it, it), LDA, a);
+      inv_upper16(a, x);
+      col_store(sm.D, 17, x);
+    }
     __syncthreads();
     v4d x = vzero();
     const int jt = it + 1 + wave;  // at most nt - 1 - it <= 7 tiles: one per wave
@@ -264,7 +292,12 @@ __device__ void inv_upper_lds(Smem& sm, int nt) {
 __device__ void inv_unit_lower_lds(Smem& sm, int nt) {
   const int wave = threadIdx.x >> 6;
   for (int it = 0; it < nt; ++it) {
-    if (wave == 0) tile_inv_unit_lower(tile(sm, it, it), LDA, sm.D, 17);
+    if (wave == 0) {
+      double a[TS], x[TS];
+      col_load(tile(sm, it, it), LDA, a);
+      inv_unit_lower16(a, x);
+      col_store(sm.D, 17, x);
+    }
     __syncthreads();
     v4d x = vzero();
     const int jt = wave;  // jt < it <= 7: one per wave
@@ -302,8 +335,7 @@ __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const doubl
   const int nbp = nt * TS;
   if (tid == 0) sm.fail = 0;
   double m = 0.0;
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
     const double v = (i < n && j < n) ? G[i + (int64_t)j * ldg] : (i == j ? 1.0 : 0.0);
     sm.A[i + j * LDA] = v;
     if (i < n && j < n) {
@@ -327,13 +359,13 @@ __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const doubl
   }
   __syncthreads();
   chol_lds(sm, n, nt, thr);
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
+    const int idx = i + j * nbp;
     R[idx] = sm.A[i + j * LDA];
   }
   inv_upper_lds(sm, nt);
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
+    const int idx = i + j * nbp;
     Ri[idx] = sm.A[i + j * LDA];
   }
   if (tid == 0) {
@@ -362,8 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nbp = nt * TS;
   if (tid == 0) sm.fail = 0;
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
     sm.A[i + j * LDA] = (i < n && j < n) ? QT[i + j * ldq] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
@@ -372,31 +403,38 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
     double* Akk = tile(sm, kt, kt);
     if (wave == 0) {
       bool bad = false;
+      double a[TS], x[TS];
+      col_load(Akk, LDA, a);
+#pragma unroll
       for (int c = 0; c < TS; ++c) {
-        const double p = Akk[c + c * LDA];
+        const double p = rl(a[c], c);
         const bool last = square && k0 + c == n - 1;
         double sg = p >= 0.0 ? -1.0 : 1.0;  // s = -sign(p), sign(0) = +1
         if (last) sg = -sg;
         if (!last && k0 + c < n && !(fabs(p) < 1.0 - 0x1p-50)) bad = true;
         const double u = last ? 0.0 : p - sg;
-        wave_sync();
-        if (lane == 0) {
-          Akk[c + c * LDA] = u;
-          sm.sgn[k0 + c] = sg;
+        const double ui = last ? 0.0 : 1.0 / u;
+        const double ucj = a[c];  // U(c, lane)
+#pragma unroll
+        for (int i = c + 1; i < TS; ++i) {
+          const double lic = rl(a[i], c) * ui;
+          if (lane > c) a[i] -= lic * ucj;
         }
-        if (lane > c && lane < TS && !last) Akk[lane + c * LDA] /= u;  // L(lane, c)
-        wave_sync();
-        for (int e = lane; e < TS * TS; e += 64) {
-          const int i = e & 15, j = e >> 4;
-          if (i > c && j > c) Akk[i + j * LDA] -= Akk[i + c * LDA] * Akk[c + j * LDA];
+        if (lane == c) {
+          a[c] = u;
+#pragma unroll
+          for (int i = c + 1; i < TS; ++i) a[i] *= ui;  // L(i, c)
         }
-        wave_sync();
+        if (lane == 0) sm.sgn[k0 + c] = sg;
       }
-      tile_inv_unit_lower(Akk, LDA, sm.D, 17);  // L_kk^-1
-      wave_sync();
-      // U_kk^-1 from the upper part of the packed tile (u = 0 only for the
-      // last column of a square panel, whose inverse is never used)
-      tile_inv_upper(Akk, LDA, sm.D2, 17);
+      col_store(Akk, LDA, a);  // packed L \ U
+      inv_unit_lower16(a, x);
+      col_store(sm.D, 17, x);  // L_kk^-1
+      double y[TS];
+#pragma unroll
+      for (int i = 0; i < TS; ++i) y[i] = i > lane ? 0.0 : a[i];
+      inv_upper16(y, x);
+      col_store(sm.D2, 17, x);  // U_kk^-1 (unused for the last tile of a square panel)
       if (bad && lane == 0) sm.fail = 1;
     }
     __syncthreads();
@@ -427,8 +465,8 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
     __syncthreads();
   }
   // Outputs from the packed L\U.
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
+    const int idx = i + j * nbp;
     const double a = sm.A[i + j * LDA];
     LUs[idx] = a;
     US[idx] = i <= j ? a * sm.sgn[j] : 0.0;
@@ -440,26 +478,25 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
   }
   __syncthreads();
   // U^-1 (square panels: the last diagonal entry is 0 and U^-1 is unused)
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
     if (i > j) sm.A[i + j * LDA] = 0.0;
   }
   __syncthreads();
   if (!square) inv_upper_lds(sm, nt);
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
+    const int idx = i + j * nbp;
     Ui[idx] = sm.A[i + j * LDA];
   }
   __syncthreads();
   // L1^-1
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
+    const int idx = i + j * nbp;
     sm.A[i + j * LDA] = i > j ? LUs[idx] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
   inv_unit_lower_lds(sm, nt);
-  for (int idx = tid; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
+    const int idx = i + j * nbp;
     Li[idx] = sm.A[i + j * LDA];
   }
   if (tid == 0 && sm.fail) *flag = 1;
@@ -473,8 +510,7 @@ __global__ __launch_bounds__(kThreads) void k_tri_inv(int n, int nt, const doubl
                                                       int64_t ldxi, int upper) {
   __shared__ Smem sm;
   const int nbp = nt * TS;
-  for (int idx = threadIdx.x; idx < nbp * nbp; idx += kThreads) {
-    const int i = idx % nbp, j = idx / nbp;
+  for (int j = elem_j0(nbp), i = (threadIdx.x) % nbp; j < nbp; j += kThreads / nbp) {
     double v = i == j ? 1.0 : 0.0;
     if (i < n && j < n && (upper ? i <= j : i > j)) v = X[i + (int64_t)j * ldx];
     sm.A[i + j * LDA] = v;
