@@ -98,7 +98,7 @@ def profile_begin():
     _check(lib().randutv_profile_begin(), "randutv_profile_begin")
 
 
-def profile_end(max_classes=32):
+def profile_end(max_classes=64):
     """Per kernel class: {name: (milliseconds, algorithmic flops, launches)}."""
     ms = (ctypes.c_double * max_classes)()
     fl = (ctypes.c_double * max_classes)()

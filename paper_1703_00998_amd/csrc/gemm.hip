@@ -76,25 +76,31 @@ struct Slabs<PREC_BF16X3, BM, BN> {
   alignas(16) __bf16 Bl[2][4][BN][8];
 };
 
-// BM x BN output tile per 256-thread workgroup; 2 x 2 waves, each owning a
-// (BM/2) x (BN/2) quarter as (BM/32) x (BN/32) MFMA 16 x 16 blocks.  The
-// occupancy hint keeps registers low enough for two workgroups per CU, so
-// one workgroup's loads overlap the other's MFMAs (measured in FP64: 128 x
-// 128 tiles at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26 without it).
+// BM x BN output tile per workgroup of WM x WN waves, each owning a
+// (BM/WM) x (BN/WN) part as MFMA 16 x 16 blocks.  Square 128 x 128 and
+// 64 x 64 tiles use 2 x 2 waves with an occupancy hint for two workgroups
+// per CU, so one workgroup's loads overlap the other's MFMAs (measured in
+// FP64: 128 x 128 tiles at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26
+// without it).  Thin outputs (one side 256 = b) take 128 x 256 / 256 x 128
+// tiles of 2 x 4 / 4 x 2 waves, one workgroup per CU, so that the long
+// operand is streamed once instead of once per 128-wide tile column.
 // Operands are FP64 in memory for every arithmetic; the loader converts.
-template <int P, bool TA, bool TB, int BM, int BN>
-__global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, int kper,
-                                                 const double* __restrict__ A, int64_t lda,
-                                                 const double* __restrict__ B, int64_t ldb,
-                                                 double* __restrict__ C, int64_t ldc,
-                                                 int64_t zstride, double alpha, double beta) {
+template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
+    int M, int N, int K, int kper, const double* __restrict__ A, int64_t lda,
+    const double* __restrict__ B, int64_t ldb, double* __restrict__ C, int64_t ldc,
+    int64_t zstride, double alpha, double beta) {
+  constexpr int NT = 64 * WM * WN;                     // threads
   constexpr int BK = Cfg<P>::BK;
-  constexpr int FM = BM / 32, FN = BN / 32;              // MFMA blocks per wave
-  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;  // elements per thread
+  constexpr int PM = BM / WM, PN = BN / WN;            // per-wave part
+  constexpr int FM = PM / 16, FN = PN / 16;            // MFMA blocks per wave
+  constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // elements per thread
+  static_assert(LA * NT == BM * BK && LB * NT == BN * BK, "loader shape");
+  static_assert(NT % BM == 0 && NT % BN == 0 && NT % BK == 0, "loader shape");
   __shared__ Slabs<P, BM, BN> sl;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WM, wn = wave / WM;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
   const int kbeg = blockIdx.z * kper;
   const int kend = min(K, kbeg + kper);
@@ -103,12 +109,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, int kper,
   // Element r of this thread's share of the A (BM x BK) and B (BK x BN)
   // slabs, chosen so that consecutive threads read consecutive addresses.
   auto a_idx = [&](int r, int& i, int& k) {
-    if (!TA) { i = tid % BM; k = tid / BM + (256 / BM) * r; }
-    else     { k = tid % BK; i = tid / BK + (256 / BK) * r; }
+    if (!TA) { i = tid % BM; k = tid / BM + (NT / BM) * r; }
+    else     { k = tid % BK; i = tid / BK + (NT / BK) * r; }
   };
   auto b_idx = [&](int r, int& k, int& j) {
-    if (!TB) { k = tid % BK; j = tid / BK + (256 / BK) * r; }
-    else     { j = tid % BN; k = tid / BN + (256 / BN) * r; }
+    if (!TB) { k = tid % BK; j = tid / BK + (NT / BK) * r; }
+    else     { j = tid % BN; k = tid / BN + (NT / BN) * r; }
   };
   double ra[LA], rb[LB];
   auto load = [&](int k0) {
@@ -157,14 +163,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, int kper,
   };
 
   using AccT = typename std::conditional<P == PREC_FP64, v4d, v4f>::type;
-  AccT acc[FM][FN], acc2[FM][FN];
+  AccT acc[FM][FN];
 #pragma unroll
   for (int x = 0; x < FM; ++x)
 #pragma unroll
-    for (int y = 0; y < FN; ++y) {
-      acc[x][y] = AccT{0, 0, 0, 0};
-      acc2[x][y] = AccT{0, 0, 0, 0};
-    }
+    for (int y = 0; y < FN; ++y) acc[x][y] = AccT{0, 0, 0, 0};
 
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   if (nk > 0) {
@@ -180,30 +183,36 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, int kper,
       v8bf ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
       for (int x = 0; x < FM; ++x) {
-        ah[x] = *(const v8bf*)&sl.Ah[cur][kr][wm * (BM / 2) + x * 16 + cr][0];
-        al[x] = *(const v8bf*)&sl.Al[cur][kr][wm * (BM / 2) + x * 16 + cr][0];
+        ah[x] = *(const v8bf*)&sl.Ah[cur][kr][wm * PM + x * 16 + cr][0];
+        al[x] = *(const v8bf*)&sl.Al[cur][kr][wm * PM + x * 16 + cr][0];
       }
 #pragma unroll
       for (int y = 0; y < FN; ++y) {
-        bh[y] = *(const v8bf*)&sl.Bh[cur][kr][wn * (BN / 2) + y * 16 + cr][0];
-        bl[y] = *(const v8bf*)&sl.Bl[cur][kr][wn * (BN / 2) + y * 16 + cr][0];
+        bh[y] = *(const v8bf*)&sl.Bh[cur][kr][wn * PN + y * 16 + cr][0];
+        bl[y] = *(const v8bf*)&sl.Bl[cur][kr][wn * PN + y * 16 + cr][0];
       }
+      // One FP32 accumulator takes the two cross terms, then hi*hi; the
+      // passes run over all blocks so consecutive MFMAs are independent.
 #pragma unroll
       for (int x = 0; x < FM; ++x)
 #pragma unroll
-        for (int y = 0; y < FN; ++y) {
-          acc[x][y] = mfmabf(bh[y], ah[x], acc[x][y]);
-          acc2[x][y] = mfmabf(bh[y], al[x], acc2[x][y]);
-          acc2[x][y] = mfmabf(bl[y], ah[x], acc2[x][y]);
-        }
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bh[y], al[x], acc[x][y]);
+#pragma unroll
+      for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bl[y], ah[x], acc[x][y]);
+#pragma unroll
+      for (int x = 0; x < FM; ++x)
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bh[y], ah[x], acc[x][y]);
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         typename std::conditional<P == PREC_FP64, double, float>::type a[FM], b[FN];
 #pragma unroll
-        for (int x = 0; x < FM; ++x) a[x] = sl.A[cur][kk + kr][wm * (BM / 2) + x * 16 + cr];
+        for (int x = 0; x < FM; ++x) a[x] = sl.A[cur][kk + kr][wm * PM + x * 16 + cr];
 #pragma unroll
-        for (int y = 0; y < FN; ++y) b[y] = sl.B[cur][kk + kr][wn * (BN / 2) + y * 16 + cr];
+        for (int y = 0; y < FN; ++y) b[y] = sl.B[cur][kk + kr][wn * PN + y * 16 + cr];
 #pragma unroll
         for (int x = 0; x < FM; ++x)
 #pragma unroll
@@ -223,19 +232,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm(int M, int N, int K, int kper,
   // ((lane>>4) + 4r) for FP64, (4(lane>>4) + r) otherwise.
 #pragma unroll
   for (int x = 0; x < FM; ++x) {
-    const int row = m0 + wm * (BM / 2) + x * 16 + cr;
+    const int row = m0 + wm * PM + x * 16 + cr;
     if (row >= M) continue;
 #pragma unroll
     for (int y = 0; y < FN; ++y) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int col = n0 + wn * (BN / 2) + y * 16 + (P == PREC_FP64 ? kr + 4 * r : 4 * kr + r);
+        const int col = n0 + wn * PN + y * 16 + (P == PREC_FP64 ? kr + 4 * r : 4 * kr + r);
         if (col < N) {
           double* p = C + row + (int64_t)col * ldc;
-          double v;
-          if constexpr (P == PREC_BF16X3) v = (double)acc[x][y][r] + (double)acc2[x][y][r];
-          else v = (double)acc[x][y][r];
-          v *= alpha;
+          double v = alpha * (double)acc[x][y][r];
           if (beta != 0.0) v += beta * *p;
           *p = v;
         }
@@ -261,30 +267,35 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ 
   }
 }
 
-template <int P, bool TA, bool TB, int BM, int BN>
+template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN>
 void launch(hipStream_t st, dim3 grid, int M, int N, int K, int kper, const double* A,
             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
             int64_t zstride, double alpha, double beta) {
-  hipLaunchKernelGGL((k_gemm<P, TA, TB, BM, BN>), grid, dim3(256), 0, st, M, N, K, kper, A, lda,
-                     B, ldb, C, ldc, zstride, alpha, beta);
+  hipLaunchKernelGGL((k_gemm<P, TA, TB, BM, BN, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, K,
+                     kper, A, lda, B, ldb, C, ldc, zstride, alpha, beta);
 }
 
-template <int P, int BM, int BN>
+template <int P, int BM, int BN, int WM, int WN>
 void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, int kper,
               const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
               int64_t ldc, int64_t zs, double al, double be) {
-  if (!ta && !tb) launch<P, false, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (ta && !tb) launch<P, true, false, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (!ta && tb) launch<P, false, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else launch<P, true, true, BM, BN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  if (!ta && !tb) launch<P, false, false, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (ta && !tb) launch<P, true, false, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (!ta && tb) launch<P, false, true, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else launch<P, true, true, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
+// Tile shapes: 0 = 64 x 64, 1 = 128 x 128, 2 = 128 x 256 (thin N), 3 = 256 x 128 (thin M).
 template <int P>
-void launch_p(hipStream_t st, bool big, bool ta, bool tb, dim3 grid, int M, int N, int K,
+void launch_p(hipStream_t st, int shape, bool ta, bool tb, dim3 grid, int M, int N, int K,
               int kper, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
               int64_t ldc, int64_t zs, double al, double be) {
-  if (big) launch_t<P, 128, 128>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else launch_t<P, 64, 64>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  switch (shape) {
+    case 1: launch_t<P, 128, 128, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
+    case 2: launch_t<P, 128, 256, 2, 4>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
+    case 3: launch_t<P, 256, 128, 4, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
+    default: launch_t<P, 64, 64, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
+  }
 }
 
 }  // namespace
@@ -300,14 +311,25 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   // blockIdx.z until about two workgroups per CU are in flight.
   const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
   const bool big = t128 >= 384 || (splitws && K >= 2048 && t128 * std::min(8, K / 512) >= 384);
-  const int BMs = big ? 128 : 64, BNs = big ? 128 : 64;
+  // Thin outputs with a long reduction (the b = 256 side of the sampling and
+  // W / C products) take a tile spanning that side, split-K supplying the
+  // workgroups; else square tiles.
+  int shape = big ? 1 : 0;
+  if (splitws && K >= 2048) {
+    if (N > 128 && N <= 256 && M >= 2048) shape = 2;
+    else if (M > 128 && M <= 256 && N >= 2048) shape = 3;
+  }
+  const int BMs = shape == 3 ? 256 : (shape == 0 ? 64 : 128);
+  const int BNs = shape == 2 ? 256 : (shape == 0 ? 64 : 128);
   const int tm = (M + BMs - 1) / BMs, tn = (N + BNs - 1) / BNs;
   const int tiles = tm * tn;
   int splits = 1;
   if (splitws && tiles < 512 && K >= 1024) {
-    // Small outputs (Gram matrices of tall panels) split deeper.
+    // Small outputs (Gram matrices of tall panels) split deeper; one-per-CU
+    // thin tiles aim at one workgroup per CU.
     const bool small = tiles <= 32;
-    splits = ((small ? 1024 : 512) + tiles - 1) / tiles;
+    const int target = small ? 1024 : (shape >= 2 ? 256 : 512);
+    splits = (target + tiles - 1) / tiles;
     splits = std::min(splits, K / (small ? 256 : 512));
     splits = std::min(splits, small ? kMaxSplitKSmall : kMaxSplitK);
     while (splits > 1 && (size_t)splits * M * N > splitws_elems) --splits;
@@ -330,12 +352,12 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   }
   const int slot = prof_mark(st);
   if (prec == PREC_FP32)
-    launch_p<PREC_FP32>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+    launch_p<PREC_FP32>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else if (prec == PREC_BF16X3)
-    launch_p<PREC_BF16X3>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+    launch_p<PREC_BF16X3>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else
-    launch_p<PREC_FP64>(st, big, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  prof_done(st, slot, 12 * (big ? 1 : 0) + 4 * (int)prec +
+    launch_p<PREC_FP64>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  prof_done(st, slot, 12 * shape + 4 * (int)prec +
                           (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN)),
             2.0 * M * N * (double)K);
   hipError_t e = hipGetLastError();

@@ -2,6 +2,7 @@
 // around each instrumented kernel (thin GEMMs, split-K reductions, panel QR,
 // small SVDs).  Off unless randutv_profile_begin() was called; not
 // thread-safe (one factorization at a time per process while profiling).
+#include <string>
 #include <vector>
 
 #include "../../include/randutv.h"
@@ -33,15 +34,19 @@ hipEvent_t take_event() {
 }
 
 // Class names: gemm_<op(A)op(B)>_<arithmetic>_<tile>, e.g. gemm_nt_fp32_t128
-// is k_gemm<PREC_FP32, false, true, 128, 128>.
-const char* kNames[PC_COUNT] = {
-    "gemm_nn_fp64_t64",    "gemm_tn_fp64_t64",    "gemm_nt_fp64_t64",    "gemm_tt_fp64_t64",
-    "gemm_nn_fp32_t64",    "gemm_tn_fp32_t64",    "gemm_nt_fp32_t64",    "gemm_tt_fp32_t64",
-    "gemm_nn_bf16x3_t64",  "gemm_tn_bf16x3_t64",  "gemm_nt_bf16x3_t64",  "gemm_tt_bf16x3_t64",
-    "gemm_nn_fp64_t128",   "gemm_tn_fp64_t128",   "gemm_nt_fp64_t128",   "gemm_tt_fp64_t128",
-    "gemm_nn_fp32_t128",   "gemm_tn_fp32_t128",   "gemm_nt_fp32_t128",   "gemm_tt_fp32_t128",
-    "gemm_nn_bf16x3_t128", "gemm_tn_bf16x3_t128", "gemm_nt_bf16x3_t128", "gemm_tt_bf16x3_t128",
-    "splitk_reduce",       "panel_qr",            "small_svd"};
+// is k_gemm<PREC_FP32, false, true, 128, 128, 2, 2>; t128x256 and t256x128
+// are the thin-output tiles.
+std::string class_name(int c) {
+  if (c == PC_SPLITK) return "splitk_reduce";
+  if (c == PC_PANEL) return "panel_qr";
+  if (c == PC_SVD) return "small_svd";
+  static const char* ops[4] = {"nn", "tn", "nt", "tt"};
+  static const char* precs[3] = {"fp64", "fp32", "bf16x3"};
+  static const char* tiles[4] = {"t64", "t128", "t128x256", "t256x128"};
+  return std::string("gemm_") + ops[c % 4] + "_" + precs[(c / 4) % 3] + "_" + tiles[c / 12];
+}
+
+std::vector<std::string> g_names;
 
 }  // namespace
 
@@ -107,7 +112,9 @@ int randutv_profile_end(int max_classes, double* ms, double* flops, int64_t* lau
 }
 
 const char* randutv_profile_class_name(int cls) {
-  return cls >= 0 && cls < PC_COUNT ? kNames[cls] : "";
+  if (g_names.empty())
+    for (int c = 0; c < PC_COUNT; ++c) g_names.push_back(class_name(c));
+  return cls >= 0 && cls < PC_COUNT ? g_names[cls].c_str() : "";
 }
 
 }  // extern "C"

@@ -30,6 +30,7 @@ namespace {
 
 constexpr int MAXN = 1024;
 constexpr int kBW = 16;          // Jacobi block width
+constexpr int kRoundThreads = 64 * kBW;  // one wave per column pair of a sub-round
 constexpr int kMaxLdsN = 256;    // largest order handled by the LDS block kernel
 
 __device__ inline double wave_sum(double v) {
@@ -192,7 +193,7 @@ __global__ void k_bj_init(const int* __restrict__ nbs, int ld, const double* __r
     for (int s = threadIdx.x; s < max_sweeps; s += blockDim.x) rotcount[mi * max_sweeps + s] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_bj_round(const int* __restrict__ nbs, int ld,
+__global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restrict__ nbs, int ld,
                                                   double* __restrict__ Wk, double* __restrict__ Vk,
                                                   int64_t strideUV, int* __restrict__ rotcount,
                                                   int max_sweeps, int sweep, int round) {
@@ -217,7 +218,7 @@ __global__ __launch_bounds__(256) void k_bj_round(const int* __restrict__ nbs, i
     const int g = blk * kBW + (c % kBW);
     return (blk < nblk && g < nb) ? g : -1;
   };
-  for (int idx = tid; idx < 2 * kBW * nb; idx += 256) {
+  for (int idx = tid; idx < 2 * kBW * nb; idx += kRoundThreads) {
     const int c = idx / nb, i = idx % nb;
     const int g = gcol(c);
     sW[c * ldl + i] = g >= 0 ? W[i + (int64_t)g * ld] : 0.0;
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void k_bj_round(const int* __restrict__ nbs, i
   // each of the two blocks.
   if (round == 0) {
     for (int r = 0; r < kBW - 1; ++r) {
-      for (int k = wave; k < kBW; k += 4) {
+      for (int k = wave; k < kBW; k += kRoundThreads / 64) {
         const int half = k / (kBW / 2), kk = k % (kBW / 2);
         int p, q;
         rr_pair(kBW, r, kk, &p, &q);
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(256) void k_bj_round(const int* __restrict__ nbs, i
   // Cross pairs (p in block bp, q in block bq): kBW sub-rounds of kBW
   // disjoint pairs (k, kBW + (k + r) mod kBW).
   for (int r = 0; r < kBW; ++r) {
-    for (int k = wave; k < kBW; k += 4) {
+    for (int k = wave; k < kBW; k += kRoundThreads / 64) {
       const int p = k, q = kBW + (k + r) % kBW;
       if (gcol(p) < 0 || gcol(q) < 0) continue;
       if (rotate_pair(sW + p * ldl, sW + q * ldl, sV + p * ldl, sV + q * ldl, nb, lane, tol) &&
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void k_bj_round(const int* __restrict__ nbs, i
     __syncthreads();
   }
   const bool any = srot != 0;
-  for (int idx = tid; idx < 2 * kBW * nb; idx += 256) {
+  for (int idx = tid; idx < 2 * kBW * nb; idx += kRoundThreads) {
     const int c = idx / nb, i = idx % nb;
     const int g = gcol(c);
     if (g >= 0) {
@@ -379,7 +380,7 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
   const int nblk2 = nblk + (nblk & 1);
   for (int sw = 0; sw < max_sweeps; ++sw)
     for (int r = 0; r < nblk2 - 1; ++r)
-      hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(256), shmem, st, nb_dev, ld, Wk,
+      hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st, nb_dev, ld, Wk,
                          Vk, strideUV, rotcount, max_sweeps, sw, r);
   hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(256), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
                      Vs, D, strideD, rotcount, max_sweeps, status);
