@@ -257,7 +257,7 @@ def main():
     ms_k, fl_k, nl = gem[dom]
     _, op, dom_prec, tile = dom.split("_")
     sym = (f"k_gemm<PREC_{dom_prec.upper()}, {'true' if op[0] == 't' else 'false'}, "
-           f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}>")
+           f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, 2, 2>")
     achieved = fl_k / (ms_k * 1e-3) / 1e12
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[2] / args.steps,
                    "avg_launch_us": (v[0] / v[2] * 1e3) if v[2] else 0.0,

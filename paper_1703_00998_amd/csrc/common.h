@@ -31,12 +31,12 @@ enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 constexpr int kPrecMixed = 3;
 
 // ---------------------------------------------------------------- timing
-// Profiling classes: thin GEMMs per tile shape (0: 64 x 64, 1: 128 x 128,
-// 2: 128 x 256, 3: 256 x 128), arithmetic (FP64, FP32, BF16x3) and transpose
-// case (class = 12*shape + 4*prec + 2*tb + ta; one class is one kernel
-// instantiation), then the other kernels.
+// Profiling classes: thin GEMMs per tile shape (0: 64 x 64, 1: 128 x 128),
+// arithmetic (FP64, FP32, BF16x3) and transpose case (class = 12*shape +
+// 4*prec + 2*tb + ta; one class is one kernel instantiation), then the
+// other kernels.
 enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
-                 PC_SPLITK = 48, PC_PANEL, PC_SVD, PC_COUNT };
+                 PC_SPLITK = 24, PC_PANEL, PC_SVD, PC_COUNT };
 bool prof_on();
 int prof_mark(hipStream_t st);  // start event; returns a slot or -1 when off
 void prof_suppress(int delta);  // +1 / -1 around launches timed by an enclosing mark

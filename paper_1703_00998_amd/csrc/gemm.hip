@@ -77,14 +77,12 @@ struct Slabs<PREC_BF16X3, BM, BN> {
 };
 
 // BM x BN output tile per workgroup of WM x WN waves, each owning a
-// (BM/WM) x (BN/WN) part as MFMA 16 x 16 blocks.  Square 128 x 128 and
-// 64 x 64 tiles use 2 x 2 waves with an occupancy hint for two workgroups
-// per CU, so one workgroup's loads overlap the other's MFMAs (measured in
-// FP64: 128 x 128 tiles at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26
-// without it).  Thin outputs (one side 256 = b) take 128 x 256 / 256 x 128
-// tiles of 2 x 4 / 4 x 2 waves, one workgroup per CU, so that the long
-// operand is streamed once instead of once per 128-wide tile column.
-// Operands are FP64 in memory for every arithmetic; the loader converts.
+// (BM/WM) x (BN/WN) part as MFMA 16 x 16 blocks.  The 128 x 128 and 64 x 64
+// tiles use 2 x 2 waves with an occupancy hint for two workgroups per CU,
+// so one workgroup's loads overlap the other's MFMAs (measured in FP64:
+// 128 x 128 tiles at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26 without
+// it).  Operands are FP64 in memory for every arithmetic; the loader
+// converts.
 template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
     int M, int N, int K, int kper, const double* __restrict__ A, int64_t lda,
@@ -285,17 +283,13 @@ void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, 
   else launch<P, true, true, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
-// Tile shapes: 0 = 64 x 64, 1 = 128 x 128, 2 = 128 x 256 (thin N), 3 = 256 x 128 (thin M).
+// Tile shapes: 0 = 64 x 64, 1 = 128 x 128, both on 2 x 2 waves.
 template <int P>
 void launch_p(hipStream_t st, int shape, bool ta, bool tb, dim3 grid, int M, int N, int K,
               int kper, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
               int64_t ldc, int64_t zs, double al, double be) {
-  switch (shape) {
-    case 1: launch_t<P, 128, 128, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
-    case 2: launch_t<P, 128, 256, 2, 4>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
-    case 3: launch_t<P, 256, 128, 4, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
-    default: launch_t<P, 64, 64, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be); break;
-  }
+  if (shape == 1) launch_t<P, 128, 128, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else launch_t<P, 64, 64, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
 }  // namespace
@@ -311,25 +305,18 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   // blockIdx.z until about two workgroups per CU are in flight.
   const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
   const bool big = t128 >= 384 || (splitws && K >= 2048 && t128 * std::min(8, K / 512) >= 384);
-  // Thin outputs with a long reduction (the b = 256 side of the sampling and
-  // W / C products) take a tile spanning that side, split-K supplying the
-  // workgroups; else square tiles.
-  int shape = big ? 1 : 0;
-  if (splitws && K >= 2048) {
-    if (N > 128 && N <= 256 && M >= 2048) shape = 2;
-    else if (M > 128 && M <= 256 && N >= 2048) shape = 3;
-  }
-  const int BMs = shape == 3 ? 256 : (shape == 0 ? 64 : 128);
-  const int BNs = shape == 2 ? 256 : (shape == 0 ? 64 : 128);
+  // (Tiles spanning the thin b = 256 side with one workgroup per CU were
+  // measured slower than two 128 x 128 workgroups per CU on every thin
+  // product of the step, in all three arithmetics.)
+  const int shape = big ? 1 : 0;
+  const int BMs = shape ? 128 : 64, BNs = shape ? 128 : 64;
   const int tm = (M + BMs - 1) / BMs, tn = (N + BNs - 1) / BNs;
   const int tiles = tm * tn;
   int splits = 1;
   if (splitws && tiles < 512 && K >= 1024) {
-    // Small outputs (Gram matrices of tall panels) split deeper; one-per-CU
-    // thin tiles aim at one workgroup per CU.
+    // Small outputs (Gram matrices of tall panels) split deeper.
     const bool small = tiles <= 32;
-    const int target = small ? 1024 : (shape >= 2 ? 256 : 512);
-    splits = (target + tiles - 1) / tiles;
+    splits = ((small ? 1024 : 512) + tiles - 1) / tiles;
     splits = std::min(splits, K / (small ? 256 : 512));
     splits = std::min(splits, small ? kMaxSplitKSmall : kMaxSplitK);
     while (splits > 1 && (size_t)splits * M * N > splitws_elems) --splits;

@@ -34,15 +34,14 @@ hipEvent_t take_event() {
 }
 
 // Class names: gemm_<op(A)op(B)>_<arithmetic>_<tile>, e.g. gemm_nt_fp32_t128
-// is k_gemm<PREC_FP32, false, true, 128, 128, 2, 2>; t128x256 and t256x128
-// are the thin-output tiles.
+// is k_gemm<PREC_FP32, false, true, 128, 128, 2, 2>.
 std::string class_name(int c) {
   if (c == PC_SPLITK) return "splitk_reduce";
   if (c == PC_PANEL) return "panel_qr";
   if (c == PC_SVD) return "small_svd";
   static const char* ops[4] = {"nn", "tn", "nt", "tt"};
   static const char* precs[3] = {"fp64", "fp32", "bf16x3"};
-  static const char* tiles[4] = {"t64", "t128", "t128x256", "t256x128"};
+  static const char* tiles[2] = {"t64", "t128"};
   return std::string("gemm_") + ops[c % 4] + "_" + precs[(c / 4) % 3] + "_" + tiles[c / 12];
 }
 
