@@ -58,6 +58,29 @@ __device__ inline v4d tile_mma(v4d acc, const double* A, int lda, const double* 
   return acc;
 }
 
+// As tile_mma<false, false>, reading A and / or B as a triangle of a
+// packed diagonal tile: mask 1 keeps the upper part (with the diagonal), 2
+// the strictly lower part with a unit diagonal; 0 reads the whole tile.
+__device__ inline double tri_mask(double v, int r, int c, int mask) {
+  if (mask == 1) return r <= c ? v : 0.0;
+  if (mask == 2) return r > c ? v : (r == c ? 1.0 : 0.0);
+  return v;
+}
+
+__device__ inline v4d tile_mma_m(v4d acc, const double* A, int lda, int ma, const double* B,
+                                 int ldb, int mb) {
+  const int l = threadIdx.x & 63;
+  const int i = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int kk = 0; kk < TS; kk += 4) {
+    const int k = kk + kq;
+    const double a = tri_mask(A[i + k * lda], i, k, ma);
+    const double b = tri_mask(B[k + i * ldb], k, i, mb);
+    acc = mfma(a, b, acc);
+  }
+  return acc;
+}
+
 __device__ inline v4d tile_load(const double* X, int ld) {
   const int l = threadIdx.x & 63;
   v4d v;
@@ -207,10 +230,15 @@ __device__ inline void upper_pair(int t, int n, int& a, int& b) {
   b = a + t;
 }
 
-// Right-looking blocked upper Cholesky A = R^T R in place (nt tiles).  A
-// pivot at or below thr (a real column, index < n) marks failure and is
-// replaced by 1 so that the factorization stays finite.
-__device__ void chol_lds(Smem& sm, int n, int nt, double thr) {
+// Right-looking blocked upper Cholesky A = R^T R (nt tiles) with R^-1 built
+// in the same loop: at step kt, after R_kk and R(kt, kt+1:) are formed, block
+// column kt of R is final; it is written to Rg (global, ld nbp) and then
+// replaced in LDS by block column kt of X = R^-1:
+//   X(i, kt) = -sum_{k=i}^{kt-1} X(i, k) (R(k, kt) R_kk^-1),  X(kt, kt) = R_kk^-1.
+// On return sm.A holds X (upper, zeros below); Rg holds R (upper part only;
+// the caller zeroes below).  A pivot at or below thr in a real column
+// (index < n) marks failure and is replaced by 1 so that all stays finite.
+__device__ void chol_inv_lds(Smem& sm, int n, int nt, double thr, double* __restrict__ Rg) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nbp = nt * TS;
   for (int kt = 0; kt < nt; ++kt) {
@@ -227,26 +255,51 @@ __device__ void chol_lds(Smem& sm, int n, int nt, double thr) {
       if (bad && lane == 0) sm.fail = 1;
     }
     __syncthreads();
-    // row panel R(kt, jt) = R_kk^-T A(kt, jt)
-    for (int jt = kt + 1 + wave; jt < nt; jt += kWaves) {
-      double* At = tile(sm, kt, jt);
-      const v4d acc = tile_mma<true, false>(vzero(), sm.D, 17, At, LDA);
-      tile_store(At, LDA, acc);
+    // row panel R(kt, jt) = R_kk^-T A(kt, jt); block column kt of R to Rg,
+    // then R(k, kt) <- R(k, kt) R_kk^-1 for k < kt
+    const int nrow = nt - 1 - kt;
+    for (int t = wave; t < nrow + kt + 1; t += kWaves) {
+      if (t < nrow) {
+        double* At = tile(sm, kt, kt + 1 + t);
+        tile_store(At, LDA, tile_mma<true, false>(vzero(), sm.D, 17, At, LDA));
+      } else {
+        const int k = t - nrow;
+        double* Ak = tile(sm, k, kt);
+        const v4d r = tile_load(Ak, LDA);
+        tile_store(Rg + k * TS + (int64_t)kt * TS * nbp, nbp, r);
+        if (k < kt) tile_store(Ak, LDA, tile_mma<false, false>(vzero(), Ak, LDA, sm.D, 17));
+      }
     }
     __syncthreads();
-    // trailing A(it, jt) -= R(kt, it)^T R(kt, jt), kt < it <= jt
-    const int nr = nt - 1 - kt;
-    for (int t = wave; t < nr * (nr + 1) / 2; t += kWaves) {
-      int a, b;
-      upper_pair(t, nr, a, b);
-      const int it = kt + 1 + a, jt = kt + 1 + b;
-      double* At = tile(sm, it, jt);
-      v4d acc = tile_load(At, LDA);
-      const v4d p = tile_mma<true, false>(vzero(), tile(sm, kt, it), LDA, tile(sm, kt, jt), LDA);
+    // trailing A(it, jt) -= R(kt, it)^T R(kt, jt) (kt < it <= jt) and block
+    // column kt of the inverse (into registers until every reader is done)
+    const int ntr = nrow * (nrow + 1) / 2;
+    v4d xi = vzero();
+    int myi = -1;
+    for (int t = wave; t < kt + ntr; t += kWaves) {
+      if (t < kt) {
+        const int i = t;
+        v4d z = vzero();
+        for (int k = i; k < kt; ++k)
+          z = tile_mma_m(z, tile(sm, i, k), LDA, k == i ? 1 : 0, tile(sm, k, kt), LDA, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] -= p[r];
-      tile_store(At, LDA, acc);
+        for (int r = 0; r < 4; ++r) xi[r] = -z[r];
+        myi = i;
+      } else {
+        int a, b;
+        upper_pair(t - kt, nrow, a, b);
+        const int it = kt + 1 + a, jt = kt + 1 + b;
+        double* At = tile(sm, it, jt);
+        v4d acc = tile_load(At, LDA);
+        const v4d p = tile_mma<true, false>(vzero(), tile(sm, kt, it), LDA, tile(sm, kt, jt), LDA);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] -= p[r];
+        tile_store(At, LDA, acc);
+      }
     }
+    __syncthreads();
+    if (myi >= 0) tile_store(tile(sm, myi, kt), LDA, xi);
+    if (wave == kWaves - 1) tile_store(Akk, LDA, tile_load(sm.D, 17));
     __syncthreads();
   }
   for (int j = elem_j0(nbp), i = (threadIdx.x) % nbp; j < nbp; j += kThreads / nbp) {
@@ -358,15 +411,11 @@ __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const doubl
     thr = 0.5;
   }
   __syncthreads();
-  chol_lds(sm, n, nt, thr);
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    const int idx = i + j * nbp;
-    R[idx] = sm.A[i + j * LDA];
-  }
-  inv_upper_lds(sm, nt);
+  chol_inv_lds(sm, n, nt, thr, R);
   for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
     const int idx = i + j * nbp;
     Ri[idx] = sm.A[i + j * LDA];
+    if (i > j) R[idx] = 0.0;
   }
   if (tid == 0) {
     if (overwrite) *flag = sm.fail;
@@ -378,7 +427,9 @@ __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const doubl
 // with an identity block), with s_k = -sign(pivot) chosen as the pivot is
 // reached (sign(0) = +1), so |u_kk| = |pivot| + 1 >= 1.  Outputs:
 //   V(0:n, 0:n) = L1 (unit lower, explicit ones and zeros), ld ldv;
-//   Ui = U^-1, Li = L1^-1, US = U S (nbp x nbp, ld nbp); LUs: packed L\U;
+//   Ui = U^-1, Li = L1^-1, US = U S (nbp x nbp, ld nbp), the inverses built
+//   in the factorization loop (block column kt of U^-1 and block row kt of
+//   L1^-1 once U(:, kt) and L1(kt, :) are final);
 //   tau_k = -u_kk s_k;  Rout = S * RF (upper, zeros below) if Rout != NULL.
 // Flags a column whose pivot has |p| >= 1 - 2^-50: its tail below the
 // diagonal is zero, where dlarfg takes tau = 0 instead.  The one exception
@@ -386,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const doubl
 // there dlarfg keeps alpha (tau = 0, R(n,n) = alpha), which is s = sign(p)
 // and u = 0 here.
 __global__ __launch_bounds__(kThreads) void k_hr_lu(
-    int n, int nt, int square, const double* __restrict__ QT, int ldq, double* __restrict__ LUs,
+    int n, int nt, int square, const double* __restrict__ QT, int ldq,
     double* __restrict__ Ui, double* __restrict__ Li, double* __restrict__ US,
     const double* __restrict__ RF, int ldrf, double* __restrict__ V, int64_t ldv,
     double* __restrict__ Rout, int64_t ldr, double* __restrict__ tau, int* flag) {
@@ -426,6 +477,7 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
           for (int i = c + 1; i < TS; ++i) a[i] *= ui;  // L(i, c)
         }
         if (lane == 0) sm.sgn[k0 + c] = sg;
+        if (lane == 0 && k0 + c < n) tau[k0 + c] = -u * sg;
       }
       col_store(Akk, LDA, a);  // packed L \ U
       inv_unit_lower16(a, x);
@@ -438,66 +490,113 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
       if (bad && lane == 0) sm.fail = 1;
     }
     __syncthreads();
-    // U(kt, jt) = L_kk^-1 A(kt, jt); L(it, kt) = A(it, kt) U_kk^-1
+    // U(kt, jt) = L_kk^-1 A(kt, jt), L(it, kt) = A(it, kt) U_kk^-1 (it, jt > kt).
+    // Block column kt of U and block row kt of L are then final: US = U S and
+    // the top of V go out, and they are replaced by U(k, kt) U_kk^-1 and
+    // L_kk^-1 L(kt, k) (k < kt) for the inverses.
     const int nr = nt - 1 - kt;
-    for (int t = wave; t < 2 * nr; t += kWaves) {
+    for (int t = wave; t < 2 * nr + 2 * kt + 1; t += kWaves) {
       if (t < nr) {
         double* At = tile(sm, kt, kt + 1 + t);
-        const v4d acc = tile_mma<false, false>(vzero(), sm.D, 17, At, LDA);
-        tile_store(At, LDA, acc);
-      } else {
+        tile_store(At, LDA, tile_mma<false, false>(vzero(), sm.D, 17, At, LDA));
+      } else if (t < 2 * nr) {
         double* At = tile(sm, kt + 1 + (t - nr), kt);
-        const v4d acc = tile_mma<false, false>(vzero(), At, LDA, sm.D2, 17);
+        tile_store(At, LDA, tile_mma<false, false>(vzero(), At, LDA, sm.D2, 17));
+      } else if (t < 2 * nr + kt + 1) {  // U(k, kt), k <= kt
+        const int k = t - 2 * nr;
+        double* At = tile(sm, k, kt);
+        const int l = lane;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = (l >> 4) + 4 * r, j = l & 15;
+          const int gi = k * TS + i, gj = kt * TS + j;
+          const double u = (k < kt || i <= j) ? At[i + j * LDA] : 0.0;
+          US[gi + (int64_t)gj * nbp] = u * sm.sgn[gj];
+        }
+        if (k < kt) tile_store(At, LDA, tile_mma<false, false>(vzero(), At, LDA, sm.D2, 17));
+      } else {  // L(kt, k), k < kt, and the diagonal block's unit lower part
+        const int k = t - 2 * nr - kt - 1;
+        double* At = tile(sm, kt, k);
+        const int l = lane;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = (l >> 4) + 4 * r, j = l & 15;
+          const int gi = kt * TS + i, gj = k * TS + j;
+          if (gi < n && gj < n) V[gi + (int64_t)gj * ldv] = At[i + j * LDA];
+        }
+        tile_store(At, LDA, tile_mma<false, false>(vzero(), sm.D, 17, At, LDA));
+      }
+    }
+    if (wave == 0) {  // diagonal block of V (unit lower) and the tile's columns above it
+      const int l = lane;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = (l >> 4) + 4 * r, j = l & 15;
+        const int gi = k0 + i, gj = k0 + j;
+        if (gi < n && gj < n) V[gi + (int64_t)gj * ldv] = i > j ? Akk[i + j * LDA] : (i == j ? 1.0 : 0.0);
+      }
+      for (int e = l; e < k0 * TS; e += 64) {  // V(0:k0, tile kt) = 0
+        const int gi = e % k0, gj = k0 + e / k0;
+        if (gj < n) V[gi + (int64_t)gj * ldv] = 0.0;
+      }
+    }
+    __syncthreads();
+    // trailing A(it, jt) -= L(it, kt) U(kt, jt), and block column kt of U^-1
+    // and block row kt of L^-1 (packed diagonal tiles read through masks):
+    //   X(i, kt) = -sum_{k=i}^{kt-1} X(i, k) U'(k, kt),
+    //   Y(kt, j) = -sum_{k=j}^{kt-1} L'(kt, k) Y(k, j).
+    v4d xi = vzero(), yj = vzero();
+    int myi = -1, myj = -1;
+    for (int t = wave; t < 2 * kt + nr * nr; t += kWaves) {
+      if (t < kt) {
+        const int i = t;
+        v4d z = vzero();
+        for (int k = i; k < kt; ++k)
+          z = tile_mma_m(z, tile(sm, i, k), LDA, k == i ? 1 : 0, tile(sm, k, kt), LDA, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xi[r] = -z[r];
+        myi = i;
+      } else if (t < 2 * kt) {
+        const int j = t - kt;
+        v4d z = vzero();
+        for (int k = j; k < kt; ++k)
+          z = tile_mma_m(z, tile(sm, kt, k), LDA, 0, tile(sm, k, j), LDA, k == j ? 2 : 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yj[r] = -z[r];
+        myj = j;
+      } else {
+        const int u = t - 2 * kt;
+        const int it = kt + 1 + u % nr, jt = kt + 1 + u / nr;
+        double* At = tile(sm, it, jt);
+        v4d acc = tile_load(At, LDA);
+        const v4d p = tile_mma<false, false>(vzero(), tile(sm, it, kt), LDA, tile(sm, kt, jt), LDA);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] -= p[r];
         tile_store(At, LDA, acc);
       }
     }
     __syncthreads();
-    // trailing A(it, jt) -= L(it, kt) U(kt, jt)
-    for (int t = wave; t < nr * nr; t += kWaves) {
-      const int it = kt + 1 + t % nr, jt = kt + 1 + t / nr;
-      double* At = tile(sm, it, jt);
-      v4d acc = tile_load(At, LDA);
-      const v4d p = tile_mma<false, false>(vzero(), tile(sm, it, kt), LDA, tile(sm, kt, jt), LDA);
+    if (myi >= 0) tile_store(tile(sm, myi, kt), LDA, xi);
+    if (myj >= 0) tile_store(tile(sm, kt, myj), LDA, yj);
+    if (wave == kWaves - 1) {  // packed inverse of the diagonal block
+      const int l = lane;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] -= p[r];
-      tile_store(At, LDA, acc);
+      for (int r = 0; r < 4; ++r) {
+        const int i = (l >> 4) + 4 * r, j = l & 15;
+        Akk[i + j * LDA] = i <= j ? sm.D2[i + j * 17] : sm.D[i + j * 17];
+      }
     }
     __syncthreads();
   }
-  // Outputs from the packed L\U.
+  // Outputs: U^-1 and L1^-1 from the packed inverses; tau and S R.
   for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
     const int idx = i + j * nbp;
     const double a = sm.A[i + j * LDA];
-    LUs[idx] = a;
-    US[idx] = i <= j ? a * sm.sgn[j] : 0.0;
-    if (i < n && j < n) {
-      V[i + (int64_t)j * ldv] = i > j ? a : (i == j ? 1.0 : 0.0);
-      if (Rout) Rout[i + (int64_t)j * ldr] = i <= j ? sm.sgn[i] * RF[i + (int64_t)j * ldrf] : 0.0;
-      if (i == j) tau[j] = -a * sm.sgn[j];
-    }
-  }
-  __syncthreads();
-  // U^-1 (square panels: the last diagonal entry is 0 and U^-1 is unused)
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    if (i > j) sm.A[i + j * LDA] = 0.0;
-  }
-  __syncthreads();
-  if (!square) inv_upper_lds(sm, nt);
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    const int idx = i + j * nbp;
-    Ui[idx] = sm.A[i + j * LDA];
-  }
-  __syncthreads();
-  // L1^-1
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    const int idx = i + j * nbp;
-    sm.A[i + j * LDA] = i > j ? LUs[idx] : (i == j ? 1.0 : 0.0);
-  }
-  __syncthreads();
-  inv_unit_lower_lds(sm, nt);
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    const int idx = i + j * nbp;
-    Li[idx] = sm.A[i + j * LDA];
+    Ui[idx] = i <= j ? a : 0.0;
+    Li[idx] = i > j ? a : (i == j ? 1.0 : 0.0);
+    if (i > j) US[idx] = 0.0;
+    if (i < n && j < n && Rout)
+      Rout[i + (int64_t)j * ldr] = i <= j ? sm.sgn[i] * RF[i + (int64_t)j * ldrf] : 0.0;
   }
   if (tid == 0 && sm.fail) *flag = 1;
 }
@@ -591,7 +690,7 @@ hipError_t hr_block(hipStream_t st, int Mp, int n, const double* P, int64_t ldp,
               nullptr, 0));
   // Householder reconstruction: LU of Q(0:n,:) - S; V top block, tau, S R.
   hipLaunchKernelGGL(k_hr_lu, dim3(1), dim3(kThreads), 0, st, n, nt, Mp == n ? 1 : 0, hw.QT, nbp,
-                     hw.LU, hw.Ui, hw.Li, hw.US, hw.RF, nbp, V, ldv, Rout, ldr, tau, hw.flag);
+                     hw.Ui, hw.Li, hw.US, hw.RF, nbp, V, ldv, Rout, ldr, tau, hw.flag);
   // V(n:Mp, :) = Q(n:Mp, :) U^-1 = Q1(n:Mp, :) (R2^-1 U^-1); Tw = -U S L1^-T.
   if (Mp > n) {
     HR_CHK(gemm(st, PREC_FP64, false, false, n, n, n, 1.0, hw.R2i, nbp, hw.Ui, nbp, 0.0, hw.R1i,
