@@ -48,6 +48,46 @@ def flops_total(m, n, q, form_uv=True):
     return f
 
 
+def kernel_sources_sha256():
+    """Digest of the GEMM kernel's sources (the template, its launch code and
+    the shared header): a measured traffic figure is reported only while the
+    sources it was taken from are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1703_00998_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_record(cls, workload):
+    """HBM bytes per launch of GEMM class `cls` on `workload`, from a
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, each scaled
+    by the same counter on a plain device copy of known size) whose line
+    `traffic-record: {json}` names that class and workload and the current
+    kernel sources' digest; None when no such summary exists."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    digest = kernel_sources_sha256()
+    for f in sorted(os.listdir(d)):
+        if not f.endswith(".md"):
+            continue
+        with open(os.path.join(d, f)) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record: "):
+                    continue
+                try:
+                    r = json.loads(line[len("traffic-record: "):])
+                except ValueError:
+                    continue
+                if (r.get("class") == cls and r.get("workload") == workload
+                        and r.get("kernel_sources_sha256") == digest):
+                    r["file"] = "profiles/" + f
+                    return r
+    return None
+
+
 def cpu_baseline(n_sample, b, q):
     """The FP64 oracle, as is, on an n_sample x n_sample matrix with the same
     per-block spectral decay, block size and q (U and V formed)."""
@@ -252,30 +292,35 @@ def main():
     # tiles are also launched inside the panel factorizations, which are
     # timed as a whole under panel_qr).
     gem = {k: v for k, v in prof.items()
-           if k.startswith("gemm") and not k.endswith("fp64_t64") and v[2] > 0}
+           if k.startswith("gemm") and not k.endswith("fp64_t64") and v[3] > 0}
     dom = max(gem, key=lambda k: gem[k][0])
-    ms_k, fl_k, nl = gem[dom]
+    ms_k, fl_k, by_k, nl = gem[dom]
     _, op, dom_prec, tile = dom.split("_")
     sym = (f"k_gemm<PREC_{dom_prec.upper()}, {'true' if op[0] == 't' else 'false'}, "
            f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, 2, 2>")
     achieved = fl_k / (ms_k * 1e-3) / 1e12
-    kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[2] / args.steps,
-                   "avg_launch_us": (v[0] / v[2] * 1e3) if v[2] else 0.0,
-                   "tflops": (v[1] / (v[0] * 1e-3) / 1e12) if v[0] > 0 and v[1] > 0 else None}
-               for k, v in prof.items() if v[2] > 0}
+    kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[3] / args.steps,
+                   "avg_launch_us": (v[0] / v[3] * 1e3) if v[3] else 0.0,
+                   "tflops": (v[1] / (v[0] * 1e-3) / 1e12) if v[0] > 0 and v[1] > 0 else None,
+                   "algorithmic_gb_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
+               for k, v in prof.items() if v[3] > 0}
     log(f"kernels [{head}]: {json.dumps(kernels)}")
+    workload = f"randUTV {m}x{n}, b={b}, q={q}, U and V formed, sigma_j=exp(-j/800)+1e-10"
+    rec = traffic_record(dom, workload)
     roof = {"bound": "mfma", "kernel": sym, "class": dom, "achieved": achieved,
             "peak": PEAK_TFLOPS[dom_prec], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS[dom_prec], "traffic": None,
-            "avg_launch_us": ms_k / nl * 1e3, "flops_per_launch": fl_k / nl}
+            "frac": achieved / PEAK_TFLOPS[dom_prec],
+            "traffic": rec["traffic_bytes_per_launch"] if rec else None,
+            "traffic_source": rec["file"] if rec else None,
+            "avg_launch_us": ms_k / nl * 1e3, "flops_per_launch": fl_k / nl,
+            "algorithmic_bytes_per_launch": by_k / nl}
     summary = {p: {k: v for k, v in d.items() if k != "prof"} for p, d in paths.items()}
     out = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[head], "data": "synthetic",
-        "config": {"workload": f"randUTV {m}x{n}, b={b}, q={q}, U and V formed, "
-                               f"sigma_j=exp(-j/800)+1e-10",
+        "config": {"workload": workload,
                    "m": m, "n": n, "b": b, "q": q, "path": head,
                    "flops_per_step": F},
         "accuracy": paths[head]["accuracy"], "error_bound": ERR_BOUND[head],

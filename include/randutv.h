@@ -200,11 +200,17 @@ int randutv_small_svd(int64_t count, const int* nbs, int64_t ld, const double* R
  * around each thin GEMM, split-K reduction, panel QR and small-SVD launch of
  * later calls; randutv_profile_end() waits for them and fills, per kernel
  * class c < max_classes (names from randutv_profile_class_name(c)), the
- * summed milliseconds, algorithmic flops (2*M*N*K per GEMM) and launch
- * counts.  Returns the number of classes filled, or a negative status.  Not
- * thread-safe; meant for one process-wide measurement at a time. */
+ * summed milliseconds, algorithmic flops (2*M*N*K per GEMM), algorithmic
+ * bytes (each operand read once and the output written once, 8 bytes per
+ * element: 8*(M*K + K*N + M*N) per GEMM, plus 8*M*N when beta != 0; a
+ * split-K reduction 8*(splits+1)*M*N, plus 8*M*N when beta != 0; a panel QR
+ * 16*Mp*nb; 0 for the small SVDs) and launch counts.  Any of ms, flops,
+ * bytes, launches may be NULL.  Returns the number of classes filled, or a
+ * negative status.  Not thread-safe; meant for one process-wide measurement
+ * at a time. */
 int randutv_profile_begin(void);
-int randutv_profile_end(int max_classes, double* ms, double* flops, int64_t* launches);
+int randutv_profile_end(int max_classes, double* ms, double* flops, double* bytes,
+                        int64_t* launches);
 const char* randutv_profile_class_name(int cls);
 
 /* Short text for a status code (static storage). */

@@ -64,7 +64,7 @@ def lib():
     L.randutv_profile_begin.argtypes = []
     L.randutv_profile_begin.restype = i32
     L.randutv_profile_end.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
-                                      ctypes.POINTER(i64)]
+                                      ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     L.randutv_profile_end.restype = i32
     L.randutv_profile_class_name.argtypes = [i32]
     L.randutv_profile_class_name.restype = ctypes.c_char_p
@@ -99,14 +99,16 @@ def profile_begin():
 
 
 def profile_end(max_classes=64):
-    """Per kernel class: {name: (milliseconds, algorithmic flops, launches)}."""
+    """Per kernel class: {name: (milliseconds, algorithmic flops, algorithmic
+    bytes, launches)}."""
     ms = (ctypes.c_double * max_classes)()
     fl = (ctypes.c_double * max_classes)()
+    by = (ctypes.c_double * max_classes)()
     ln = (ctypes.c_int64 * max_classes)()
-    nc = lib().randutv_profile_end(max_classes, ms, fl, ln)
+    nc = lib().randutv_profile_end(max_classes, ms, fl, by, ln)
     if nc < 0:
         _check(nc, "randutv_profile_end")
-    return {lib().randutv_profile_class_name(c).decode(): (ms[c], fl[c], int(ln[c]))
+    return {lib().randutv_profile_class_name(c).decode(): (ms[c], fl[c], by[c], int(ln[c]))
             for c in range(nc)}
 
 

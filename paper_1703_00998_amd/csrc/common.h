@@ -40,7 +40,8 @@ enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
 bool prof_on();
 int prof_mark(hipStream_t st);  // start event; returns a slot or -1 when off
 void prof_suppress(int delta);  // +1 / -1 around launches timed by an enclosing mark
-void prof_done(hipStream_t st, int slot, int cls, double flops);
+// flops and bytes: the launch's algorithmic work and HBM operand traffic.
+void prof_done(hipStream_t st, int slot, int cls, double flops, double bytes);
 
 // ---------------------------------------------------------------- GEMM
 // C(M x N) = alpha * op(A) * op(B) + beta * C, column-major, op = transpose

@@ -346,7 +346,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     launch_p<PREC_FP64>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   prof_done(st, slot, 12 * shape + 4 * (int)prec +
                           (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN)),
-            2.0 * M * N * (double)K);
+            2.0 * M * N * (double)K,
+            8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;
   const int64_t total = (int64_t)M * N;
@@ -354,7 +355,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   const int slot2 = prof_mark(st);
   hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, st, M, N, splits, splitws,
                      zs, C, ldc, alpha, beta);
-  prof_done(st, slot2, PC_SPLITK, (double)splits * M * N);
+  prof_done(st, slot2, PC_SPLITK, (double)splits * M * N,
+            8.0 * (double)M * N * (splits + (beta != 0.0 ? 2 : 1)));
   return hipGetLastError();
 }
 

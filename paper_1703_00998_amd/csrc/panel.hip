@@ -976,7 +976,7 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
       const int slot = prof_mark(st);
       hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel_lds, dim3(nwg), dim3(256),
                                                 args, (unsigned)shmem, st);
-      prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb);
+      prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb, 16.0 * Mp * (double)nb);
       return e;
     }
   }
@@ -992,7 +992,7 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
   void* args[] = {&a};
   const int slot = prof_mark(st);
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel, dim3(nwg), dim3(256), args, 0, st);
-  prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb);
+  prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb, 16.0 * Mp * (double)nb);
   return e;
 }
 

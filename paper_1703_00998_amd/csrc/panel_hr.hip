@@ -762,7 +762,7 @@ hipError_t panel_qr_hr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, d
   if (e == hipSuccess) e = panel_qr(st, Mp, nb, P, ldp, tau, Tw, ldtw, pw, hw.flag);
   if (e == hipSuccess) e = panel_extract(st, Mp, nb, P, ldp, V, ldv, Rout, ldr, hw.flag);
   prof_suppress(-1);
-  prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb);
+  prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb, 16.0 * Mp * (double)nb);
   return e == hipSuccess ? hipGetLastError() : e;
 }
 

@@ -14,7 +14,7 @@ namespace {
 struct Rec {
   hipEvent_t a, b;
   int cls;
-  double flops;
+  double flops, bytes;
 };
 
 bool g_on = false;
@@ -58,15 +58,16 @@ int prof_mark(hipStream_t st) {
   hipEvent_t a = take_event(), b = take_event();
   if (!a || !b) return -1;
   if (hipEventRecord(a, st) != hipSuccess) return -1;
-  g_recs.push_back(Rec{a, b, -1, 0.0});
+  g_recs.push_back(Rec{a, b, -1, 0.0, 0.0});
   return (int)g_recs.size() - 1;
 }
 
-void prof_done(hipStream_t st, int slot, int cls, double flops) {
+void prof_done(hipStream_t st, int slot, int cls, double flops, double bytes) {
   if (slot < 0 || slot >= (int)g_recs.size()) return;
   Rec& r = g_recs[slot];
   r.cls = cls;
   r.flops = flops;
+  r.bytes = bytes;
   (void)hipEventRecord(r.b, st);
 }
 
@@ -86,12 +87,14 @@ int randutv_profile_begin(void) {
   return 0;
 }
 
-int randutv_profile_end(int max_classes, double* ms, double* flops, int64_t* launches) {
+int randutv_profile_end(int max_classes, double* ms, double* flops, double* bytes,
+                        int64_t* launches) {
   g_on = false;
   const int nc = max_classes < PC_COUNT ? max_classes : PC_COUNT;
   for (int c = 0; c < nc; ++c) {
     if (ms) ms[c] = 0.0;
     if (flops) flops[c] = 0.0;
+    if (bytes) bytes[c] = 0.0;
     if (launches) launches[c] = 0;
   }
   int status = 0;
@@ -101,6 +104,7 @@ int randutv_profile_end(int max_classes, double* ms, double* flops, int64_t* lau
     if (r.cls >= 0 && r.cls < nc && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
       if (ms) ms[r.cls] += t;
       if (flops) flops[r.cls] += r.flops;
+      if (bytes) bytes[r.cls] += r.bytes;
       if (launches) launches[r.cls] += 1;
     }
     g_pool.push_back(r.a);

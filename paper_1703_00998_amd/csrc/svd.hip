@@ -361,7 +361,7 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
   if (ld > kMaxLdsN) {
     hipLaunchKernelGGL(k_jacobi, dim3(count), dim3(256), 0, st, nb_dev, ld, R, strideR, Us, Vs,
                        strideUV, D, strideD, Wk, Vk, status, max_sweeps);
-    prof_done(st, slot, PC_SVD, 0.0);
+    prof_done(st, slot, PC_SVD, 0.0, 0.0);
     return hipGetLastError();
   }
   static bool attr_set = false;
@@ -384,7 +384,7 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
                          Vk, strideUV, rotcount, max_sweeps, sw, r);
   hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(256), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
                      Vs, D, strideD, rotcount, max_sweeps, status);
-  prof_done(st, slot, PC_SVD, 0.0);
+  prof_done(st, slot, PC_SVD, 0.0, 0.0);
   return hipGetLastError();
 }
 
