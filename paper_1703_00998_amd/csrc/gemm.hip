@@ -99,10 +99,26 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int kbeg = blockIdx.z * kper;
+  // Tile order.  Workgroups go to the 8 XCDs round-robin by linear id, and
+  // each XCD has its own L2.  Linear id L runs on XCD L % 8 as that XCD's
+  // (L / 8)-th workgroup; giving every XCD one contiguous range of the tile
+  // sequence, walked down groups of 8 tile rows, keeps the workgroups that
+  // one XCD holds at once on a compact patch of C, so the A row-tiles and B
+  // column-tiles they read are shared in that XCD's L2.
+  const int tm = gridDim.x, tn = gridDim.y;
+  const int tiles = tm * tn, total = tiles * (int)gridDim.z;
+  const int lin = blockIdx.x + tm * (blockIdx.y + tn * (int)blockIdx.z);
+  const int xcd = lin & 7, per = total >> 3, extra = total & 7;
+  const int seq = xcd * per + min(xcd, extra) + (lin >> 3);
+  const int bz = seq / tiles, rem = seq - bz * tiles;
+  constexpr int kGroup = 8;
+  const int g0 = rem / (kGroup * tn) * kGroup;
+  const int gsz = min(kGroup, tm - g0);
+  const int gi = rem - g0 * tn;
+  const int m0 = (g0 + gi % gsz) * BM, n0 = (gi / gsz) * BN;
+  const int kbeg = bz * kper;
   const int kend = min(K, kbeg + kper);
-  if (gridDim.z > 1) C += (int64_t)blockIdx.z * zstride;
+  if (gridDim.z > 1) C += (int64_t)bz * zstride;
 
   // Element r of this thread's share of the A (BM x BK) and B (BK x BN)
   // slabs, chosen so that consecutive threads read consecutive addresses.

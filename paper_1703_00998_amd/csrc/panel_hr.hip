@@ -24,6 +24,7 @@
 // by one wave in LDS, with the triangular inverses built alongside, block
 // column by block column.
 #include <algorithm>
+#include <utility>
 
 #include "common.h"
 
@@ -35,6 +36,7 @@ constexpr int kWaves = 8;      // waves of the single-workgroup kernels
 constexpr int kThreads = 64 * kWaves;
 constexpr int kBlk = 128;      // widest block factored in LDS (wider panels: two blocks)
 constexpr int LDA = kBlk + 1;  // LDS leading dimension (odd: spreads the banks)
+constexpr int kLoadCols = kThreads / kBlk;  // columns per pass when loading a block
 
 __device__ inline v4d mfma(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -119,6 +121,40 @@ __device__ inline double rl(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Orders register values in program order: an empty volatile statement
+// taking the value as a read-write operand, so that the compiler neither
+// hoists the broadcasts that read it above the statement nor sinks the
+// arithmetic that writes it below the next one.  Without it all broadcasts
+// of a step are issued at once and the scalar registers spill.
+__device__ inline void pin(double& v) { asm volatile("" : "+v"(v)); }
+
+// Value of v in lane C of each row of 16 lanes (DPP row_newbcast; one
+// v_mov_b64 per double).  The four rows of a wave hold copies of the same
+// 16 columns, so every lane receives column C's value.
+template <int C>
+__device__ inline double bcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + C, 0xF, 0xF, true);
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates (relative error below
+// 2^-22, denormals supported) and two Newton steps each: a few ulp, in
+// five or six dependent FMAs instead of the IEEE division sequence.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double rsq_nr(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
 __device__ inline void col_load(const double* T, int ld, double (&a)[TS]) {
   const int j = threadIdx.x & 15;
 #pragma unroll
@@ -133,30 +169,176 @@ __device__ inline void col_store(double* T, int ld, const double (&a)[TS]) {
   }
 }
 
-// Upper Cholesky of the symmetric tile in a (both triangles present): on
-// return a holds R (zeros below the diagonal).  A pivot at or below thr in a
-// real column (k0 + c < n) is replaced by 1 and reported through bad.
-__device__ inline void chol16(double (&a)[TS], int k0, int n, double thr, bool& bad) {
-  const int lane = threadIdx.x & 63;
+constexpr int kPipe = 4;  // broadcasts in flight per group in the tile routines
+
+// The 15 rank-1 updates of step C of a 16-column elimination, as a pipeline:
+// job e < 15 - C updates row C+1+e of the eliminated matrix, a later job
+// row e-(15-C) of the inverse being accumulated; broadcasts are read kPipe
+// at a time, one group ahead of the FMAs that use them, and pin() bounds
+// how many are live.  upd(e, b) applies job e with broadcast value b.
+template <int C, typename Src, typename Upd>
+__device__ inline void step_updates(Src src, Upd upd) {
+  double bp[kPipe], bn[kPipe];
 #pragma unroll
-  for (int c = 0; c < TS; ++c) {
-    double d = rl(a[c], c);
-    if (k0 + c < n && !(d > thr)) {
-      bad = true;
-      d = 1.0;
-    }
-    const double r = sqrt(d), ri = 1.0 / r;
-    const double rcj = a[c] * ri;  // R(c, lane)
+  for (int e0 = 0; e0 < TS - 1 + kPipe; e0 += kPipe) {
 #pragma unroll
-    for (int i = c + 1; i < TS; ++i) {
-      const double lic = rl(a[i], c) * ri;
-      if (lane > c) a[i] -= lic * rcj;
+    for (int q = 0; q < kPipe; ++q) {
+      const int e = e0 + q;
+      if (e < TS - 1) {
+        double& z = src(e);
+        pin(z);
+        bn[q] = bcast<C>(z);
+      }
     }
-    if (lane >= c) a[c] = (lane == c) ? r : rcj;
+#pragma unroll
+    for (int q = 0; q < kPipe; ++q) {
+      const int e = e0 - kPipe + q;
+      if (e >= 0 && e < TS - 1) upd(e, bp[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kPipe; ++q) bp[q] = bn[q];
   }
+}
+
+// Upper Cholesky R of the symmetric tile in a (both triangles present) and
+// x = R^-1, in one sweep: the elimination runs without square roots (A =
+// U^T diag(d) U, U unit upper) so the pivot chain holds one reciprocal per
+// column, and the columns of U^-1 are accumulated right-looking from the
+// same broadcasts (column c of U^-1 is final once step c starts).  Then R =
+// diag(d)^1/2 U and R^-1 = U^-1 diag(d)^-1/2, the square roots taken once
+// per lane at the end.  On return a holds R and x
+// holds R^-1 (zeros below the diagonal).  A pivot at or below thr in a real
+// column (k0 + c < n) is replaced by 1 and reported through bad.
+template <int C>
+__device__ inline void chol_step(double (&a)[TS], double (&x)[TS], int k0, int n, double thr,
+                                 bool& bad, double& my_d) {
+  const int j = threadIdx.x & 15;
+  double d = bcast<C>(a[C]);
+  if (k0 + C < n && !(d > thr)) {
+    bad = true;
+    d = 1.0;
+  }
+  const double t = j > C ? a[C] * rcp_nr(d) : 0.0;  // U(C, j)
+  auto src = [&](int e) -> double& { return e < TS - 1 - C ? a[C + 1 + e] : x[e - (TS - 1 - C)]; };
+  step_updates<C>(src, [&](int e, double b) {
+    double& z = src(e);
+    z = fma(-b, t, z);
+    pin(z);
+  });
+  x[C] -= t;
+  if (j == C) my_d = d;
+}
+
+template <int... Cs>
+__device__ inline void chol_steps(std::integer_sequence<int, Cs...>, double (&a)[TS],
+                                  double (&x)[TS], int k0, int n, double thr, bool& bad,
+                                  double& my_d) {
+  (chol_step<Cs>(a, x, k0, n, thr, bad, my_d), ...);
+}
+
+// R(i, j) = d_i^-1/2 A(i, j) above the diagonal (row i's scale broadcast
+// from lane i), d_j^1/2 on it, zero below.  The broadcast is taken by every
+// lane before the selection (a DPP read from a lane switched off by a branch
+// returns zero).
+template <int I>
+__device__ inline void chol_scale_row(double (&a)[TS], double my_d, double my_s) {
+  const int j = threadIdx.x & 15;
+  const double si = bcast<I>(my_s);
+  a[I] = I < j ? a[I] * si : (I == j ? my_d * my_s : 0.0);
+}
+template <int... Is>
+__device__ inline void chol_scale(std::integer_sequence<int, Is...>, double (&a)[TS],
+                                  double my_d, double my_s) {
+  (chol_scale_row<Is>(a, my_d, my_s), ...);
+}
+
+__device__ inline void chol_inv16(double (&a)[TS], double (&x)[TS], int k0, int n, double thr,
+                                  bool& bad) {
+  const int j = threadIdx.x & 15;
+  double my_d = 1.0;
 #pragma unroll
-  for (int i = 0; i < TS; ++i)
-    if (i > lane) a[i] = 0.0;
+  for (int i = 0; i < TS; ++i) x[i] = i == j ? 1.0 : 0.0;
+  chol_steps(std::make_integer_sequence<int, TS>(), a, x, k0, n, thr, bad, my_d);
+  const double my_s = rsq_nr(my_d);  // d_j^-1/2
+  chol_scale(std::make_integer_sequence<int, TS>(), a, my_d, my_s);
+#pragma unroll
+  for (int i = 0; i < TS; ++i) x[i] *= my_s;
+}
+
+// LU of the tile in a minus S, S = diag(s_c) with s_c = -sign(pivot) chosen
+// as each pivot is reached (sign(0) = +1; the last column of a square panel,
+// last_col, takes s = sign(p) and u = 0 instead), with L^-1 and U^-1 built in
+// the same sweep: at step c every lane reads column c (pivot and L(:, c)) and,
+// for U^-1, column c of W = U^-1 diag(u) (final once step c starts); lanes
+// right of c update their part of A and of W with t = U(c, j) / u_cc, and
+// every lane updates its column of Y = L^-1 with Y(c, j) / u_cc (zero right
+// of c).  On return a holds L \ U packed (unit diagonal of L implied), xl =
+// L^-1 (unit lower), xu = U^-1 (zero column for u = 0).  sg_out[c] and
+// tau_out[c] (c < n) receive s_c and -u_cc s_c; bad is set for a
+// pivot with |p| >= 1 - 2^-50 in a real column other than last_col.
+struct LuState {
+  double my_ui, my_sg;
+};
+
+template <int C>
+__device__ inline void lu_step(double (&a)[TS], double (&xl)[TS], double (&xu)[TS], int k0,
+                               int n, int last_col, bool& bad, LuState& st) {
+  const int j = threadIdx.x & 15;
+  const double p = bcast<C>(a[C]);
+  const bool last = k0 + C == last_col;
+  double sg = p >= 0.0 ? -1.0 : 1.0;  // s = -sign(p), sign(0) = +1
+  if (last) sg = -sg;
+  if (!last && k0 + C < n && !(fabs(p) < 1.0 - 0x1p-50)) bad = true;
+  const double u = last ? 0.0 : p - sg;
+  const double ui = last ? 0.0 : rcp_nr(u);
+  const double t = j > C ? a[C] * ui : 0.0;  // U(C, j) / u_CC
+  const double ty = xl[C] * ui;              // Y(C, j) / u_CC
+  auto src = [&](int e) -> double& { return e < TS - 1 - C ? a[C + 1 + e] : xu[e - (TS - 1 - C)]; };
+  step_updates<C>(src, [&](int e, double b) {
+    if (e < TS - 1 - C) {  // row below C: used for A and for Y
+      const int i = C + 1 + e;
+      a[i] = fma(-b, t, a[i]);
+      xl[i] = fma(-b, ty, xl[i]);
+      pin(a[i]);
+      pin(xl[i]);
+    } else {
+      double& z = xu[e - (TS - 1 - C)];
+      z = fma(-b, t, z);
+      pin(z);
+    }
+  });
+  xu[C] -= t;
+  if (j == C) {
+    a[C] = u;
+    st.my_ui = ui;
+    st.my_sg = sg;
+  }
+}
+
+template <int... Cs>
+__device__ inline void lu_steps(std::integer_sequence<int, Cs...>, double (&a)[TS],
+                                double (&xl)[TS], double (&xu)[TS], int k0, int n, int last_col,
+                                bool& bad, LuState& st) {
+  (lu_step<Cs>(a, xl, xu, k0, n, last_col, bad, st), ...);
+}
+
+__device__ inline void lu_inv16(double (&a)[TS], double (&xl)[TS], double (&xu)[TS], int k0,
+                                int n, int last_col, double* sg_out, double* tau_out,
+                                bool& bad) {
+  const int lane = threadIdx.x & 63, j = lane & 15;
+  LuState st{0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < TS; ++i) xl[i] = xu[i] = i == j ? 1.0 : 0.0;
+  lu_steps(std::make_integer_sequence<int, TS>(), a, xl, xu, k0, n, last_col, bad, st);
+#pragma unroll
+  for (int i = 0; i < TS; ++i) {
+    if (i > j) a[i] *= st.my_ui;  // L(i, j)
+    xu[i] *= st.my_ui;
+  }
+  if (lane < TS) {
+    sg_out[k0 + lane] = st.my_sg;
+    if (k0 + lane < n) tau_out[k0 + lane] = -a[lane] * st.my_sg;
+  }
 }
 
 // x = inverse of the upper-triangular tile in a (x zero below the diagonal).
@@ -248,9 +430,8 @@ __device__ void chol_inv_lds(Smem& sm, int n, int nt, double thr, double* __rest
       bool bad = false;
       double a[TS], x[TS];
       col_load(Akk, LDA, a);
-      chol16(a, k0, n, thr, bad);
+      chol_inv16(a, x, k0, n, thr, bad);
       col_store(Akk, LDA, a);
-      inv_upper16(a, x);
       col_store(sm.D, 17, x);
       if (bad && lane == 0) sm.fail = 1;
     }
@@ -388,16 +569,30 @@ __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const doubl
   const int nbp = nt * TS;
   if (tid == 0) sm.fail = 0;
   double m = 0.0;
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    const double v = (i < n && j < n) ? G[i + (int64_t)j * ldg] : (i == j ? 1.0 : 0.0);
-    sm.A[i + j * LDA] = v;
-    if (i < n && j < n) {
-      if (pass == 1) {
-        if (i == j) m = fmax(m, v);
-      } else {
-        m = fmax(m, fabs(v - (i == j ? 1.0 : 0.0)));
+  {
+    // All loads first (clamped indices keep them in bounds), then the stores:
+    // one memory round trip instead of one per column group.
+    const int i = tid % kBlk, j0 = tid / kBlk;
+    double g[kBlk / kLoadCols];
+#pragma unroll
+    for (int r = 0; r < kBlk / kLoadCols; ++r) {
+      const int j = j0 + kLoadCols * r;
+      g[r] = G[min(i, n - 1) + (int64_t)min(j, n - 1) * ldg];
+    }
+#pragma unroll
+    for (int r = 0; r < kBlk / kLoadCols; ++r) {
+      const int j = j0 + kLoadCols * r;
+      const bool in = i < n && j < n;
+      const double v = in ? g[r] : (i == j ? 1.0 : 0.0);
+      if (i < nbp && j < nbp) sm.A[i + j * LDA] = v;
+      if (in) {
+        if (pass == 1) {
+          if (i == j) m = fmax(m, v);
+        } else {
+          m = fmax(m, fabs(v - (i == j ? 1.0 : 0.0)));
+        }
+        if (!(v == v)) m = __builtin_inf();  // NaN input: fail below
       }
-      if (!(v == v)) m = __builtin_inf();  // NaN input: fail below
     }
   }
   __syncthreads();
@@ -445,8 +640,19 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int nbp = nt * TS;
   if (tid == 0) sm.fail = 0;
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    sm.A[i + j * LDA] = (i < n && j < n) ? QT[i + j * ldq] : (i == j ? 1.0 : 0.0);
+  {
+    const int i = tid % kBlk, j0 = tid / kBlk;
+    double g[kBlk / kLoadCols];
+#pragma unroll
+    for (int r = 0; r < kBlk / kLoadCols; ++r) {
+      const int j = j0 + kLoadCols * r;
+      g[r] = QT[min(i, n - 1) + min(j, n - 1) * ldq];
+    }
+#pragma unroll
+    for (int r = 0; r < kBlk / kLoadCols; ++r) {
+      const int j = j0 + kLoadCols * r;
+      if (i < nbp && j < nbp) sm.A[i + j * LDA] = (i < n && j < n) ? g[r] : (i == j ? 1.0 : 0.0);
+    }
   }
   __syncthreads();
   for (int kt = 0; kt < nt; ++kt) {
@@ -454,39 +660,12 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
     double* Akk = tile(sm, kt, kt);
     if (wave == 0) {
       bool bad = false;
-      double a[TS], x[TS];
+      double a[TS], xl[TS], xu[TS];
       col_load(Akk, LDA, a);
-#pragma unroll
-      for (int c = 0; c < TS; ++c) {
-        const double p = rl(a[c], c);
-        const bool last = square && k0 + c == n - 1;
-        double sg = p >= 0.0 ? -1.0 : 1.0;  // s = -sign(p), sign(0) = +1
-        if (last) sg = -sg;
-        if (!last && k0 + c < n && !(fabs(p) < 1.0 - 0x1p-50)) bad = true;
-        const double u = last ? 0.0 : p - sg;
-        const double ui = last ? 0.0 : 1.0 / u;
-        const double ucj = a[c];  // U(c, lane)
-#pragma unroll
-        for (int i = c + 1; i < TS; ++i) {
-          const double lic = rl(a[i], c) * ui;
-          if (lane > c) a[i] -= lic * ucj;
-        }
-        if (lane == c) {
-          a[c] = u;
-#pragma unroll
-          for (int i = c + 1; i < TS; ++i) a[i] *= ui;  // L(i, c)
-        }
-        if (lane == 0) sm.sgn[k0 + c] = sg;
-        if (lane == 0 && k0 + c < n) tau[k0 + c] = -u * sg;
-      }
-      col_store(Akk, LDA, a);  // packed L \ U
-      inv_unit_lower16(a, x);
-      col_store(sm.D, 17, x);  // L_kk^-1
-      double y[TS];
-#pragma unroll
-      for (int i = 0; i < TS; ++i) y[i] = i > lane ? 0.0 : a[i];
-      inv_upper16(y, x);
-      col_store(sm.D2, 17, x);  // U_kk^-1 (unused for the last tile of a square panel)
+      lu_inv16(a, xl, xu, k0, n, square ? n - 1 : -1, sm.sgn, tau, bad);
+      col_store(Akk, LDA, a);    // packed L \ U
+      col_store(sm.D, 17, xl);   // L_kk^-1
+      col_store(sm.D2, 17, xu);  // U_kk^-1 (unused for the last tile of a square panel)
       if (bad && lane == 0) sm.fail = 1;
     }
     __syncthreads();
@@ -527,17 +706,13 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
         tile_store(At, LDA, tile_mma<false, false>(vzero(), sm.D, 17, At, LDA));
       }
     }
-    if (wave == 0) {  // diagonal block of V (unit lower) and the tile's columns above it
+    if (wave == 0) {  // diagonal block of V (unit lower; its zeros above come at the end)
       const int l = lane;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = (l >> 4) + 4 * r, j = l & 15;
         const int gi = k0 + i, gj = k0 + j;
         if (gi < n && gj < n) V[gi + (int64_t)gj * ldv] = i > j ? Akk[i + j * LDA] : (i == j ? 1.0 : 0.0);
-      }
-      for (int e = l; e < k0 * TS; e += 64) {  // V(0:k0, tile kt) = 0
-        const int gi = e % k0, gj = k0 + e / k0;
-        if (gj < n) V[gi + (int64_t)gj * ldv] = 0.0;
       }
     }
     __syncthreads();
@@ -588,15 +763,39 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
     }
     __syncthreads();
   }
-  // Outputs: U^-1 and L1^-1 from the packed inverses; tau and S R.
-  for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
-    const int idx = i + j * nbp;
-    const double a = sm.A[i + j * LDA];
-    Ui[idx] = i <= j ? a : 0.0;
-    Li[idx] = i > j ? a : (i == j ? 1.0 : 0.0);
-    if (i > j) US[idx] = 0.0;
-    if (i < n && j < n && Rout)
-      Rout[i + (int64_t)j * ldr] = i <= j ? sm.sgn[i] * RF[i + (int64_t)j * ldrf] : 0.0;
+  // Outputs: U^-1 and L1^-1 from the packed inverses, the zeros of V above
+  // its diagonal, then S R with the RF loads issued eight at a time.
+  {
+    const int i = tid % kBlk, j0 = tid / kBlk;
+#pragma unroll 4
+    for (int r = 0; r < kBlk / kLoadCols; ++r) {
+      const int j = j0 + kLoadCols * r;
+      if (i < nbp && j < nbp) {
+        const int idx = i + j * nbp;
+        const double a = sm.A[i + j * LDA];
+        Ui[idx] = i <= j ? a : 0.0;
+        Li[idx] = i > j ? a : (i == j ? 1.0 : 0.0);
+        if (i > j) US[idx] = 0.0;
+        if (i < j && j < n) V[i + (int64_t)j * ldv] = 0.0;
+      }
+    }
+    if (Rout) {
+      constexpr int kBatch = 8;
+#pragma unroll 1
+      for (int r0 = 0; r0 < kBlk / kLoadCols; r0 += kBatch) {
+        double rf[kBatch];
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          const int j = j0 + kLoadCols * (r0 + r);
+          rf[r] = RF[min(i, n - 1) + (int64_t)min(j, n - 1) * ldrf];
+        }
+#pragma unroll
+        for (int r = 0; r < kBatch; ++r) {
+          const int j = j0 + kLoadCols * (r0 + r);
+          if (i < n && j < n) Rout[i + (int64_t)j * ldr] = i <= j ? sm.sgn[i] * rf[r] : 0.0;
+        }
+      }
+    }
   }
   if (tid == 0 && sm.fail) *flag = 1;
 }
