@@ -374,8 +374,8 @@ __device__ inline void inv_unit_lower16(const double (&a)[TS], double (&x)[TS]) 
 // The whole (padded) matrix of a single-workgroup kernel lives in LDS.
 struct Smem {
   double A[kBlk * LDA];  // column-major, leading dimension LDA
-  double D[TS * 17];     // inverse of the current diagonal tile (ld 17)
-  double D2[TS * 17];
+  double D[2][TS * 17];  // inverses of the diagonal tiles of steps kt, kt + 1 (ld 17)
+  double D2[2][TS * 17];
   double red[kWaves];
   double sgn[kBlk];
   int fail;
@@ -423,64 +423,83 @@ __device__ inline void upper_pair(int t, int n, int& a, int& b) {
 __device__ void chol_inv_lds(Smem& sm, int n, int nt, double thr, double* __restrict__ Rg) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nbp = nt * TS;
-  for (int kt = 0; kt < nt; ++kt) {
-    const int k0 = kt * TS;
+  // Diagonal tile kt, by wave 0: R_kk into the tile, R_kk^-1 into D[kt & 1].
+  auto diag = [&](int kt) {
+    bool bad = false;
+    double a[TS], x[TS];
     double* Akk = tile(sm, kt, kt);
-    if (wave == 0) {
-      bool bad = false;
-      double a[TS], x[TS];
-      col_load(Akk, LDA, a);
-      chol_inv16(a, x, k0, n, thr, bad);
-      col_store(Akk, LDA, a);
-      col_store(sm.D, 17, x);
-      if (bad && lane == 0) sm.fail = 1;
-    }
-    __syncthreads();
+    col_load(Akk, LDA, a);
+    chol_inv16(a, x, kt * TS, n, thr, bad);
+    col_store(Akk, LDA, a);
+    col_store(sm.D[kt & 1], 17, x);
+    if (bad && lane == 0) sm.fail = 1;
+  };
+  if (wave == 0) diag(0);
+  __syncthreads();
+  for (int kt = 0; kt < nt; ++kt) {
+    const double* D = sm.D[kt & 1];
+    double* Akk = tile(sm, kt, kt);
     // row panel R(kt, jt) = R_kk^-T A(kt, jt); block column kt of R to Rg,
     // then R(k, kt) <- R(k, kt) R_kk^-1 for k < kt
     const int nrow = nt - 1 - kt;
     for (int t = wave; t < nrow + kt + 1; t += kWaves) {
       if (t < nrow) {
         double* At = tile(sm, kt, kt + 1 + t);
-        tile_store(At, LDA, tile_mma<true, false>(vzero(), sm.D, 17, At, LDA));
+        tile_store(At, LDA, tile_mma<true, false>(vzero(), D, 17, At, LDA));
       } else {
         const int k = t - nrow;
         double* Ak = tile(sm, k, kt);
         const v4d r = tile_load(Ak, LDA);
         tile_store(Rg + k * TS + (int64_t)kt * TS * nbp, nbp, r);
-        if (k < kt) tile_store(Ak, LDA, tile_mma<false, false>(vzero(), Ak, LDA, sm.D, 17));
+        if (k < kt) tile_store(Ak, LDA, tile_mma<false, false>(vzero(), Ak, LDA, D, 17));
       }
     }
     __syncthreads();
     // trailing A(it, jt) -= R(kt, it)^T R(kt, jt) (kt < it <= jt) and block
-    // column kt of the inverse (into registers until every reader is done)
+    // column kt of the inverse (into registers until every reader is done).
+    // Look-ahead: wave 0 updates tile (kt+1, kt+1) first and factors it while
+    // the other waves do the rest.
     const int ntr = nrow * (nrow + 1) / 2;
     v4d xi = vzero();
     int myi = -1;
-    for (int t = wave; t < kt + ntr; t += kWaves) {
-      if (t < kt) {
-        const int i = t;
-        v4d z = vzero();
-        for (int k = i; k < kt; ++k)
-          z = tile_mma_m(z, tile(sm, i, k), LDA, k == i ? 1 : 0, tile(sm, k, kt), LDA, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) xi[r] = -z[r];
-        myi = i;
-      } else {
-        int a, b;
-        upper_pair(t - kt, nrow, a, b);
-        const int it = kt + 1 + a, jt = kt + 1 + b;
-        double* At = tile(sm, it, jt);
+    if (wave == 0) {
+      if (nrow > 0) {
+        double* At = tile(sm, kt + 1, kt + 1);
         v4d acc = tile_load(At, LDA);
-        const v4d p = tile_mma<true, false>(vzero(), tile(sm, kt, it), LDA, tile(sm, kt, jt), LDA);
+        const double* Rk = tile(sm, kt, kt + 1);
+        const v4d p = tile_mma<true, false>(vzero(), Rk, LDA, Rk, LDA);
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] -= p[r];
         tile_store(At, LDA, acc);
+        diag(kt + 1);
+      }
+    } else {
+      const int ntask = kt + (ntr > 0 ? ntr - 1 : 0);
+      for (int t = wave - 1; t < ntask; t += kWaves - 1) {
+        if (t < kt) {
+          const int i = t;
+          v4d z = vzero();
+          for (int k = i; k < kt; ++k)
+            z = tile_mma_m(z, tile(sm, i, k), LDA, k == i ? 1 : 0, tile(sm, k, kt), LDA, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xi[r] = -z[r];
+          myi = i;
+        } else {
+          int a, b;
+          upper_pair(t - kt + 1, nrow, a, b);  // pair (0, 0) is wave 0's
+          const int it = kt + 1 + a, jt = kt + 1 + b;
+          double* At = tile(sm, it, jt);
+          v4d acc = tile_load(At, LDA);
+          const v4d p = tile_mma<true, false>(vzero(), tile(sm, kt, it), LDA, tile(sm, kt, jt), LDA);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r] -= p[r];
+          tile_store(At, LDA, acc);
+        }
       }
     }
     __syncthreads();
     if (myi >= 0) tile_store(tile(sm, myi, kt), LDA, xi);
-    if (wave == kWaves - 1) tile_store(Akk, LDA, tile_load(sm.D, 17));
+    if (wave == kWaves - 1) tile_store(Akk, LDA, tile_load(D, 17));
     __syncthreads();
   }
   for (int j = elem_j0(nbp), i = (threadIdx.x) % nbp; j < nbp; j += kThreads / nbp) {
@@ -498,7 +517,7 @@ __device__ void inv_upper_lds(Smem& sm, int nt) {
       double a[TS], x[TS];
       col_load(tile(sm, it, it), LDA, a);
       inv_upper16(a, x);
-      col_store(sm.D, 17, x);
+      col_store(sm.D[0], 17, x);
     }
     __syncthreads();
     v4d x = vzero();
@@ -507,7 +526,7 @@ __device__ void inv_upper_lds(Smem& sm, int nt) {
       v4d z = vzero();
       for (int k = it + 1; k <= jt; ++k)
         z = tile_mma<false, false>(z, tile(sm, it, k), LDA, tile(sm, k, jt), LDA);
-      x = mma_reg_b(vzero(), sm.D, 17, z);
+      x = mma_reg_b(vzero(), sm.D[0], 17, z);
     }
     __syncthreads();
     if (jt < nt) {
@@ -515,7 +534,7 @@ __device__ void inv_upper_lds(Smem& sm, int nt) {
       for (int r = 0; r < 4; ++r) x[r] = -x[r];
       tile_store(tile(sm, it, jt), LDA, x);
     }
-    if (wave == 0) tile_store(tile(sm, it, it), LDA, tile_load(sm.D, 17));
+    if (wave == 0) tile_store(tile(sm, it, it), LDA, tile_load(sm.D[0], 17));
     __syncthreads();
   }
 }
@@ -530,7 +549,7 @@ __device__ void inv_unit_lower_lds(Smem& sm, int nt) {
       double a[TS], x[TS];
       col_load(tile(sm, it, it), LDA, a);
       inv_unit_lower16(a, x);
-      col_store(sm.D, 17, x);
+      col_store(sm.D[0], 17, x);
     }
     __syncthreads();
     v4d x = vzero();
@@ -539,7 +558,7 @@ __device__ void inv_unit_lower_lds(Smem& sm, int nt) {
       v4d z = vzero();
       for (int k = jt; k < it; ++k)
         z = tile_mma<false, false>(z, tile(sm, it, k), LDA, tile(sm, k, jt), LDA);
-      x = mma_reg_b(vzero(), sm.D, 17, z);
+      x = mma_reg_b(vzero(), sm.D[0], 17, z);
     }
     __syncthreads();
     if (jt < it) {
@@ -547,7 +566,7 @@ __device__ void inv_unit_lower_lds(Smem& sm, int nt) {
       for (int r = 0; r < 4; ++r) x[r] = -x[r];
       tile_store(tile(sm, it, jt), LDA, x);
     }
-    if (wave == 0) tile_store(tile(sm, it, it), LDA, tile_load(sm.D, 17));
+    if (wave == 0) tile_store(tile(sm, it, it), LDA, tile_load(sm.D[0], 17));
     __syncthreads();
   }
 }
@@ -655,20 +674,27 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
     }
   }
   __syncthreads();
+  // Diagonal tile kt, by wave 0: packed L \ U into the tile, L_kk^-1 and
+  // U_kk^-1 (unused for the last tile of a square panel) into D[kt & 1] and
+  // D2[kt & 1].
+  auto diag = [&](int kt) {
+    bool bad = false;
+    double a[TS], xl[TS], xu[TS];
+    double* Akk = tile(sm, kt, kt);
+    col_load(Akk, LDA, a);
+    lu_inv16(a, xl, xu, kt * TS, n, square ? n - 1 : -1, sm.sgn, tau, bad);
+    col_store(Akk, LDA, a);
+    col_store(sm.D[kt & 1], 17, xl);
+    col_store(sm.D2[kt & 1], 17, xu);
+    if (bad && lane == 0) sm.fail = 1;
+  };
+  if (wave == 0) diag(0);
+  __syncthreads();
   for (int kt = 0; kt < nt; ++kt) {
     const int k0 = kt * TS;
     double* Akk = tile(sm, kt, kt);
-    if (wave == 0) {
-      bool bad = false;
-      double a[TS], xl[TS], xu[TS];
-      col_load(Akk, LDA, a);
-      lu_inv16(a, xl, xu, k0, n, square ? n - 1 : -1, sm.sgn, tau, bad);
-      col_store(Akk, LDA, a);    // packed L \ U
-      col_store(sm.D, 17, xl);   // L_kk^-1
-      col_store(sm.D2, 17, xu);  // U_kk^-1 (unused for the last tile of a square panel)
-      if (bad && lane == 0) sm.fail = 1;
-    }
-    __syncthreads();
+    const double* D = sm.D[kt & 1];
+    const double* D2 = sm.D2[kt & 1];
     // U(kt, jt) = L_kk^-1 A(kt, jt), L(it, kt) = A(it, kt) U_kk^-1 (it, jt > kt).
     // Block column kt of U and block row kt of L are then final: US = U S and
     // the top of V go out, and they are replaced by U(k, kt) U_kk^-1 and
@@ -677,10 +703,10 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
     for (int t = wave; t < 2 * nr + 2 * kt + 1; t += kWaves) {
       if (t < nr) {
         double* At = tile(sm, kt, kt + 1 + t);
-        tile_store(At, LDA, tile_mma<false, false>(vzero(), sm.D, 17, At, LDA));
+        tile_store(At, LDA, tile_mma<false, false>(vzero(), D, 17, At, LDA));
       } else if (t < 2 * nr) {
         double* At = tile(sm, kt + 1 + (t - nr), kt);
-        tile_store(At, LDA, tile_mma<false, false>(vzero(), At, LDA, sm.D2, 17));
+        tile_store(At, LDA, tile_mma<false, false>(vzero(), At, LDA, D2, 17));
       } else if (t < 2 * nr + kt + 1) {  // U(k, kt), k <= kt
         const int k = t - 2 * nr;
         double* At = tile(sm, k, kt);
@@ -692,7 +718,7 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
           const double u = (k < kt || i <= j) ? At[i + j * LDA] : 0.0;
           US[gi + (int64_t)gj * nbp] = u * sm.sgn[gj];
         }
-        if (k < kt) tile_store(At, LDA, tile_mma<false, false>(vzero(), At, LDA, sm.D2, 17));
+        if (k < kt) tile_store(At, LDA, tile_mma<false, false>(vzero(), At, LDA, D2, 17));
       } else {  // L(kt, k), k < kt, and the diagonal block's unit lower part
         const int k = t - 2 * nr - kt - 1;
         double* At = tile(sm, kt, k);
@@ -703,7 +729,7 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
           const int gi = kt * TS + i, gj = k * TS + j;
           if (gi < n && gj < n) V[gi + (int64_t)gj * ldv] = At[i + j * LDA];
         }
-        tile_store(At, LDA, tile_mma<false, false>(vzero(), sm.D, 17, At, LDA));
+        tile_store(At, LDA, tile_mma<false, false>(vzero(), D, 17, At, LDA));
       }
     }
     if (wave == 0) {  // diagonal block of V (unit lower; its zeros above come at the end)
@@ -720,34 +746,50 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
     // and block row kt of L^-1 (packed diagonal tiles read through masks):
     //   X(i, kt) = -sum_{k=i}^{kt-1} X(i, k) U'(k, kt),
     //   Y(kt, j) = -sum_{k=j}^{kt-1} L'(kt, k) Y(k, j).
+    // Look-ahead: wave 0 updates tile (kt+1, kt+1) first and factors it while
+    // the other waves do the rest.
     v4d xi = vzero(), yj = vzero();
     int myi = -1, myj = -1;
-    for (int t = wave; t < 2 * kt + nr * nr; t += kWaves) {
-      if (t < kt) {
-        const int i = t;
-        v4d z = vzero();
-        for (int k = i; k < kt; ++k)
-          z = tile_mma_m(z, tile(sm, i, k), LDA, k == i ? 1 : 0, tile(sm, k, kt), LDA, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) xi[r] = -z[r];
-        myi = i;
-      } else if (t < 2 * kt) {
-        const int j = t - kt;
-        v4d z = vzero();
-        for (int k = j; k < kt; ++k)
-          z = tile_mma_m(z, tile(sm, kt, k), LDA, 0, tile(sm, k, j), LDA, k == j ? 2 : 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) yj[r] = -z[r];
-        myj = j;
-      } else {
-        const int u = t - 2 * kt;
-        const int it = kt + 1 + u % nr, jt = kt + 1 + u / nr;
-        double* At = tile(sm, it, jt);
+    if (wave == 0) {
+      if (nr > 0) {
+        double* At = tile(sm, kt + 1, kt + 1);
         v4d acc = tile_load(At, LDA);
-        const v4d p = tile_mma<false, false>(vzero(), tile(sm, it, kt), LDA, tile(sm, kt, jt), LDA);
+        const v4d p = tile_mma<false, false>(vzero(), tile(sm, kt + 1, kt), LDA,
+                                             tile(sm, kt, kt + 1), LDA);
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[r] -= p[r];
         tile_store(At, LDA, acc);
+        diag(kt + 1);
+      }
+    } else {
+      const int ntask = 2 * kt + (nr > 0 ? nr * nr - 1 : 0);
+      for (int t = wave - 1; t < ntask; t += kWaves - 1) {
+        if (t < kt) {
+          const int i = t;
+          v4d z = vzero();
+          for (int k = i; k < kt; ++k)
+            z = tile_mma_m(z, tile(sm, i, k), LDA, k == i ? 1 : 0, tile(sm, k, kt), LDA, 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xi[r] = -z[r];
+          myi = i;
+        } else if (t < 2 * kt) {
+          const int j = t - kt;
+          v4d z = vzero();
+          for (int k = j; k < kt; ++k)
+            z = tile_mma_m(z, tile(sm, kt, k), LDA, 0, tile(sm, k, j), LDA, k == j ? 2 : 0);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yj[r] = -z[r];
+          myj = j;
+        } else {
+          const int u = t - 2 * kt + 1;  // u = 0, tile (kt+1, kt+1), is wave 0's
+          const int it = kt + 1 + u % nr, jt = kt + 1 + u / nr;
+          double* At = tile(sm, it, jt);
+          v4d acc = tile_load(At, LDA);
+          const v4d p = tile_mma<false, false>(vzero(), tile(sm, it, kt), LDA, tile(sm, kt, jt), LDA);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r] -= p[r];
+          tile_store(At, LDA, acc);
+        }
       }
     }
     __syncthreads();
@@ -758,7 +800,7 @@ __global__ __launch_bounds__(kThreads) void k_hr_lu(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = (l >> 4) + 4 * r, j = l & 15;
-        Akk[i + j * LDA] = i <= j ? sm.D2[i + j * 17] : sm.D[i + j * 17];
+        Akk[i + j * LDA] = i <= j ? D2[i + j * 17] : D[i + j * 17];
       }
     }
     __syncthreads();
