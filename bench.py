@@ -292,7 +292,8 @@ def main():
     # tiles are also launched inside the panel factorizations, which are
     # timed as a whole under panel_qr).
     gem = {k: v for k, v in prof.items()
-           if k.startswith("gemm") and not k.endswith("fp64_t64") and v[3] > 0}
+           if k.startswith("gemm") and len(k.split("_")) == 4 and not k.endswith("fp64_t64")
+           and v[3] > 0}
     dom = max(gem, key=lambda k: gem[k][0])
     ms_k, fl_k, by_k, nl = gem[dom]
     _, op, dom_prec, tile = dom.split("_")

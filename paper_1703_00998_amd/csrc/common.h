@@ -36,7 +36,7 @@ constexpr int kPrecMixed = 3;
 // 4*prec + 2*tb + ta; one class is one kernel instantiation), then the
 // other kernels.
 enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
-                 PC_SPLITK = 24, PC_PANEL, PC_SVD, PC_COUNT };
+                 PC_SPLITK = 24, PC_PANEL, PC_SVD, PC_GEMM_SMALL, PC_COUNT };
 bool prof_on();
 int prof_mark(hipStream_t st);  // start event; returns a slot or -1 when off
 void prof_suppress(int delta);  // +1 / -1 around launches timed by an enclosing mark

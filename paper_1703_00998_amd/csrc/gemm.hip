@@ -23,6 +23,8 @@ namespace rutv {
 namespace {
 
 constexpr int PAD = 2;
+constexpr int kSmallMN = 128;  // products at most this size in M and N
+constexpr int kSmallK = 512;   // and this deep go to k_gemm_small (FP64)
 
 __device__ inline v4d mfma64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -264,6 +266,59 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
   }
 }
 
+// Small FP64 products (M, N <= kSmallMN, short K: the 128 x 128 blocks of
+// the panel factorizations).  One wave per 16 x 16 tile of C, operands read
+// straight from memory (L2) into the MFMA operand registers, eight K steps
+// of loads in flight at a time and two accumulators.  Spreads a 128 x 128
+// product over 64 CUs, where the LDS-tiled kernel puts it on four.
+// Same transposed MFMA orientation as k_gemm: register r of lane l holds
+// C(m0 + (l & 15), n0 + (l >> 4) + 4 r).
+template <bool TA, bool TB>
+__global__ __launch_bounds__(64) void k_gemm_small(int M, int N, int K, const double* __restrict__ A,
+                                                    int64_t lda, const double* __restrict__ B,
+                                                    int64_t ldb, double* __restrict__ C,
+                                                    int64_t ldc, double alpha, double beta) {
+  const int lane = threadIdx.x;
+  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ia = m0 + li, jb = n0 + li;  // row of op(A), column of op(B) this lane reads
+  auto opA = [&](int k) -> double {
+    if (ia >= M || k >= K) return 0.0;
+    return TA ? A[k + (int64_t)ia * lda] : A[ia + (int64_t)k * lda];
+  };
+  auto opB = [&](int k) -> double {
+    if (jb >= N || k >= K) return 0.0;
+    return TB ? B[jb + (int64_t)k * ldb] : B[k + (int64_t)jb * ldb];
+  };
+  v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  constexpr int kSteps = 8;  // K steps of 4 per batch of loads
+  for (int k0 = 0; k0 < K; k0 += 4 * kSteps) {
+    double a[kSteps], b[kSteps];
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u) {
+      a[u] = opA(k0 + 4 * u + lk);
+      b[u] = opB(k0 + 4 * u + lk);
+    }
+#pragma unroll
+    for (int u = 0; u < kSteps; u += 2) {
+      acc0 = mfma64(b[u], a[u], acc0);
+      acc1 = mfma64(b[u + 1], a[u + 1], acc1);
+    }
+  }
+  const int row = m0 + li;
+  if (row >= M) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int col = n0 + lk + 4 * r;
+    if (col < N) {
+      double* p = C + row + (int64_t)col * ldc;
+      double v = alpha * (acc0[r] + acc1[r]);
+      if (beta != 0.0) v += beta * *p;
+      *p = v;
+    }
+  }
+}
+
 __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ P,
                                 int64_t zstride, double* __restrict__ C, int64_t ldc,
                                 double alpha, double beta) {
@@ -272,8 +327,18 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ 
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx % M);
     const int64_t j = idx / M;
+    // Partials summed in order z = 0, 1, ...; loaded eight at a time so the
+    // loads are in flight together.
     double s = 0.0;
-    for (int z = 0; z < S; ++z) s += P[z * zstride + idx];
+    int z = 0;
+    for (; z + 8 <= S; z += 8) {
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = P[(z + u) * zstride + idx];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += p[u];
+    }
+    for (; z < S; ++z) s += P[z * zstride + idx];
     double* p = C + i + j * ldc;
     double v = alpha * s;
     if (beta != 0.0) v += beta * *p;
@@ -315,6 +380,17 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
                 int64_t ldb, double beta, double* C, int64_t ldc, double* splitws,
                 size_t splitws_elems) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (prec == PREC_FP64 && M <= kSmallMN && N <= kSmallMN && K <= kSmallK) {
+    const dim3 grid((M + 15) / 16, (N + 15) / 16);
+    const int slot = prof_mark(st);
+    if (!ta && !tb) hipLaunchKernelGGL((k_gemm_small<false, false>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    else if (ta && !tb) hipLaunchKernelGGL((k_gemm_small<true, false>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    else if (!ta && tb) hipLaunchKernelGGL((k_gemm_small<false, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    else hipLaunchKernelGGL((k_gemm_small<true, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    prof_done(st, slot, PC_GEMM_SMALL, 2.0 * M * N * (double)K,
+              8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)));
+    return hipGetLastError();
+  }
   const int BK = prec == PREC_BF16X3 ? 32 : 16;
   // 128 x 128 tiles when the output, or the output times a split of K,
   // gives enough workgroups; else 64 x 64.  Long reductions are split over

@@ -39,6 +39,7 @@ std::string class_name(int c) {
   if (c == PC_SPLITK) return "splitk_reduce";
   if (c == PC_PANEL) return "panel_qr";
   if (c == PC_SVD) return "small_svd";
+  if (c == PC_GEMM_SMALL) return "gemm_small_fp64";
   static const char* ops[4] = {"nn", "tn", "nt", "tt"};
   static const char* precs[3] = {"fp64", "fp32", "bf16x3"};
   static const char* tiles[2] = {"t64", "t128"};

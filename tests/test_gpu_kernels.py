@@ -26,7 +26,8 @@ def _np(t):
 
 GEMM_SHAPES = [(64, 64, 16), (100, 70, 130), (257, 33, 1500), (8, 300, 7), (1, 1, 1),
                (130, 256, 4100), (33, 17, 0),
-               (2100, 200, 1100), (3000, 256, 700), (240, 2300, 1200)]  # thin-output tiles
+               (2100, 200, 1100), (3000, 256, 700), (240, 2300, 1200),  # thin-output tiles
+               (128, 128, 128), (128, 128, 512), (16, 128, 37), (127, 3, 513)]  # small-product path edges
 
 
 @pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
