@@ -974,8 +974,22 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
                    w.bcast, w.bpart, w.red, w.bar, w.err, gate, w.gram, w.qtop};
       void* args[] = {&a};
       const int slot = prof_mark(st);
-      hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel_lds, dim3(nwg), dim3(256),
-                                                args, (unsigned)shmem, st);
+      hipError_t e;
+      if (gate) {
+        // Gated (fallback) use: nearly always skipped, every workgroup
+        // returning at once, so it is an ordinary launch on the caller's
+        // stream; a cooperative launch goes through a queue of its own, and
+        // the two cross-queue waits cost tens of microseconds per panel.
+        // When it does run, its nwg <= CU-count workgroups (one per CU by
+        // LDS) all become resident once the other streams' workgroups drain
+        // (those streams wait on this one for new work), and every grid
+        // barrier wait is bounded (the error word is raised on timeout).
+        hipLaunchKernelGGL(k_panel_lds, dim3(nwg), dim3(256), shmem, st, a);
+        e = hipGetLastError();
+      } else {
+        e = hipLaunchCooperativeKernel((const void*)k_panel_lds, dim3(nwg), dim3(256), args,
+                                       (unsigned)shmem, st);
+      }
       prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb, 16.0 * Mp * (double)nb);
       return e;
     }
