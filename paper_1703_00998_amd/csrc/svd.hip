@@ -22,6 +22,7 @@
 // e_1, e_2, ...  Matrices wider than kMaxLdsN use a single-workgroup
 // global-memory kernel.
 #include <algorithm>
+#include <vector>
 
 #include "common.h"
 
@@ -32,6 +33,8 @@ constexpr int MAXN = 1024;
 constexpr int kBW = 16;          // Jacobi block width
 constexpr int kRoundThreads = 64 * kBW;  // one wave per column pair of a sub-round
 constexpr int kMaxLdsN = 256;    // largest order handled by the LDS block kernel
+constexpr int kFirstSweeps = 6;  // block-Jacobi sweeps launched before the first convergence check
+constexpr int kMoreSweeps = 2;   // and between later checks
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -378,10 +381,28 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
                      strideUV, rotcount, max_sweeps);
   const int nblk = (ld + kBW - 1) / kBW;
   const int nblk2 = nblk + (nblk & 1);
-  for (int sw = 0; sw < max_sweeps; ++sw)
-    for (int r = 0; r < nblk2 - 1; ++r)
-      hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st, nb_dev, ld, Wk,
-                         Vk, strideUV, rotcount, max_sweeps, sw, r);
+  // Sweeps go out in groups (kFirstSweeps, then kMoreSweeps at a time); after
+  // each group the host reads the last sweep's rotation counts and stops
+  // once every matrix had a sweep without rotations.  A converged matrix
+  // skips later rounds on the device anyway; this saves the launches.
+  std::vector<int> last(count);
+  for (int sw0 = 0; sw0 < max_sweeps;) {
+    const int sw1 = std::min(max_sweeps, sw0 + (sw0 == 0 ? kFirstSweeps : kMoreSweeps));
+    for (int sw = sw0; sw < sw1; ++sw)
+      for (int r = 0; r < nblk2 - 1; ++r)
+        hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st, nb_dev, ld, Wk,
+                           Vk, strideUV, rotcount, max_sweeps, sw, r);
+    sw0 = sw1;
+    if (sw0 >= max_sweeps) break;
+    hipError_t e = hipMemcpy2DAsync(last.data(), sizeof(int), rotcount + sw0 - 1,
+                                    (size_t)max_sweeps * sizeof(int), sizeof(int), count,
+                                    hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    bool done = true;
+    for (int v : last) done = done && v == 0;
+    if (done) break;
+  }
   hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(256), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
                      Vs, D, strideD, rotcount, max_sweeps, status);
   prof_done(st, slot, PC_SVD, 0.0, 0.0);
