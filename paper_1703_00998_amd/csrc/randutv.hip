@@ -126,19 +126,20 @@ SideCtx* side_ctx() {
 }
 
 // FP64 product for the U / V stream with the reduction cut into launches
-// of at most kSideChunk (beta = 1 after the first): each workgroup then runs
-// for microseconds, so a panel kernel on the main stream, which needs most of
-// a CU's LDS, finds a free CU quickly instead of waiting for long
-// side-stream workgroups to drain.
-constexpr int kSideChunk = 1024;
-hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, const double* A,
-                     int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                     int64_t ldc) {
-  for (int k0 = 0; k0 < K || k0 == 0; k0 += kSideChunk) {
-    const int kc = std::min(kSideChunk, K - k0);
+// of at most `chunk` (beta = 1 after the first): each workgroup then runs
+// for tens of microseconds, so a panel kernel on the main stream, which
+// needs most of a CU's LDS, finds a free CU quickly instead of waiting for
+// long side-stream workgroups to drain.
+constexpr int kSideChunk = 256;     // reduction chunk of the thin products W = X Vh
+constexpr int kSideChunkUpd = 256;  // and of the rank-b updates X -= W2 Vh^T
+hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha,
+                     const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                     double* C, int64_t ldc, int chunk) {
+  for (int k0 = 0; k0 < K || k0 == 0; k0 += chunk) {
+    const int kc = std::min(chunk, K - k0);
     const double* Ak = A + (ta ? (int64_t)k0 : (int64_t)k0 * lda);
     const double* Bk = B + (tb ? (int64_t)k0 * ldb : (int64_t)k0);
-    const hipError_t e = gemm(st, PREC_FP64, ta, tb, M, N, kc, 1.0, Ak, lda, Bk, ldb,
+    const hipError_t e = gemm(st, PREC_FP64, ta, tb, M, N, kc, alpha, Ak, lda, Bk, ldb,
                               k0 == 0 ? beta : 1.0, C, ldc, nullptr, 0);
     if (e != hipSuccess) return e;
     if (K <= 0) break;
@@ -333,9 +334,9 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
       if (formV) {  // V(:, J) = V(:, J) Vq, on the U / V stream
         double* VJ = V + (int64_t)r0 * ldv;
         HIPCHK(to_side(0 + sl));
-        HIPCHK(gemm_side(ss, false, false, N, B, Ni, VJ, ldv, Vh, N, 0.0, Ws, M));
+        HIPCHK(gemm_side(ss, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, M, kSideChunk));
         HIPCHK(gemm(ss, PREC_FP64, false, false, N, B, B, 1.0, Ws, M, TwV, B, 0.0, W2s, M, nullptr, 0));
-        HIPCHK(gemm(ss, PREC_FP64, false, true, N, Ni, B, -1.0, W2s, M, Vh, N, 1.0, VJ, ldv, nullptr, 0));
+        HIPCHK(gemm_side(ss, false, true, N, Ni, B, -1.0, W2s, M, Vh, N, 1.0, VJ, ldv, kSideChunkUpd));
         HIPCHK(side_done(4 + sl, &vpend[sl]));
       }
       // [Uq, R] = qr(T([I2,I3], J2))
@@ -352,9 +353,9 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
       if (formU) {  // on the U / V stream
         double* UI = U + (int64_t)r0 * ldu;
         HIPCHK(to_side(2 + sl));
-        HIPCHK(gemm_side(ss, false, false, M, B, Mi, UI, ldu, Uh, M, 0.0, Ws, M));
+        HIPCHK(gemm_side(ss, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, M, kSideChunk));
         HIPCHK(gemm(ss, PREC_FP64, false, false, M, B, B, 1.0, Ws, M, TwU, B, 0.0, W2s, M, nullptr, 0));
-        HIPCHK(gemm(ss, PREC_FP64, false, true, M, Mi, B, -1.0, W2s, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+        HIPCHK(gemm_side(ss, false, true, M, Mi, B, -1.0, W2s, M, Uh, M, 1.0, UI, ldu, kSideChunkUpd));
         HIPCHK(side_done(6 + sl, &upend[sl]));
       }
       // T([I2,I3], J2) = [R; 0]; R moves to the stash, the diagonal block is
