@@ -22,7 +22,6 @@
 // e_1, e_2, ...  Matrices wider than kMaxLdsN use a single-workgroup
 // global-memory kernel.
 #include <algorithm>
-#include <vector>
 
 #include "common.h"
 
@@ -385,24 +384,38 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
   // each group the host reads the last sweep's rotation counts and stops
   // once every matrix had a sweep without rotations.  A converged matrix
   // skips later rounds on the device anyway; this saves the launches.
-  std::vector<int> last(count);
-  for (int sw0 = 0; sw0 < max_sweeps;) {
-    const int sw1 = std::min(max_sweeps, sw0 + (sw0 == 0 ? kFirstSweeps : kMoreSweeps));
+  // The counts come back through pinned host memory and an event that the
+  // host polls (a blocking stream synchronization wakes up milliseconds late).
+  int* last = nullptr;
+  hipEvent_t ev = nullptr;
+  bool check = hipHostMalloc((void**)&last, (size_t)count * sizeof(int), hipHostMallocDefault) ==
+                   hipSuccess &&
+               hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+  (void)hipGetLastError();
+  hipError_t e = hipSuccess;
+  for (int sw0 = 0; sw0 < max_sweeps && e == hipSuccess;) {
+    const int sw1 = !check ? max_sweeps
+                           : std::min(max_sweeps, sw0 + (sw0 == 0 ? kFirstSweeps : kMoreSweeps));
     for (int sw = sw0; sw < sw1; ++sw)
       for (int r = 0; r < nblk2 - 1; ++r)
         hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st, nb_dev, ld, Wk,
                            Vk, strideUV, rotcount, max_sweeps, sw, r);
     sw0 = sw1;
     if (sw0 >= max_sweeps) break;
-    hipError_t e = hipMemcpy2DAsync(last.data(), sizeof(int), rotcount + sw0 - 1,
-                                    (size_t)max_sweeps * sizeof(int), sizeof(int), count,
-                                    hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
+    e = hipMemcpy2DAsync(last, sizeof(int), rotcount + sw0 - 1, (size_t)max_sweeps * sizeof(int),
+                         sizeof(int), count, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(ev, st);
+    if (e != hipSuccess) break;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) break;
     bool done = true;
-    for (int v : last) done = done && v == 0;
+    for (int i = 0; i < count; ++i) done = done && last[i] == 0;
     if (done) break;
   }
+  if (ev) (void)hipEventDestroy(ev);
+  if (last) (void)hipHostFree(last);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(256), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
                      Vs, D, strideD, rotcount, max_sweeps, status);
   prof_done(st, slot, PC_SVD, 0.0, 0.0);
