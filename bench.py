@@ -288,11 +288,12 @@ def main():
     ms_step, prof = paths[head]["ms_per_step"], paths[head]["prof"]
     value = F / (ms_step * 1e-3) / 1e12
     # Dominant kernel: the GEMM class with the most time on the headline path,
-    # among the classes whose every launch is timed on its own (FP64 64 x 64
-    # tiles are also launched inside the panel factorizations, which are
-    # timed as a whole under panel_qr).
+    # among the classes whose every launch is timed on its own (the panel
+    # factorizations, timed as a whole under panel_qr, also launch FP64
+    # 64 x 64 NN and TN tiles).
+    inside_panels = ("gemm_nn_fp64_t64", "gemm_tn_fp64_t64")
     gem = {k: v for k, v in prof.items()
-           if k.startswith("gemm") and len(k.split("_")) == 4 and not k.endswith("fp64_t64")
+           if k.startswith("gemm") and len(k.split("_")) == 4 and k not in inside_panels
            and v[3] > 0}
     dom = max(gem, key=lambda k: gem[k][0])
     ms_k, fl_k, by_k, nl = gem[dom]

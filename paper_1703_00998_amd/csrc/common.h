@@ -48,10 +48,11 @@ void prof_done(hipStream_t st, int slot, int cls, double flops, double bytes);
 // if ta/tb.  `splitws` (>= kMaxSplitK * M * N doubles, or NULL) enables
 // split-K for long reductions.  The arithmetic of the inner products is set
 // by `prec`; operands and C are FP64 in memory.
+// small_tiles forces 64 x 64 tiles (shorter workgroups, for the second stream).
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc,
-                double* splitws, size_t splitws_elems);
+                double* splitws, size_t splitws_elems, bool small_tiles = false);
 
 // ---------------------------------------------------------------- panel QR
 struct PanelWork {

@@ -378,7 +378,7 @@ void launch_p(hipStream_t st, int shape, bool ta, bool tb, dim3 grid, int M, int
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc, double* splitws,
-                size_t splitws_elems) {
+                size_t splitws_elems, bool small_tiles) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (prec == PREC_FP64 && M <= kSmallMN && N <= kSmallMN && K <= kSmallK) {
     const dim3 grid((M + 15) / 16, (N + 15) / 16);
@@ -396,7 +396,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   // gives enough workgroups; else 64 x 64.  Long reductions are split over
   // blockIdx.z until about two workgroups per CU are in flight.
   const int64_t t128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
-  const bool big = t128 >= 384 || (splitws && K >= 2048 && t128 * std::min(8, K / 512) >= 384);
+  const bool big = !small_tiles &&
+                   (t128 >= 384 || (splitws && K >= 2048 && t128 * std::min(8, K / 512) >= 384));
   // (Tiles spanning the thin b = 256 side with one workgroup per CU were
   // measured slower than two 128 x 128 workgroups per CU on every thin
   // product of the step, in all three arithmetics.)

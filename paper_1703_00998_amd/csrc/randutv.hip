@@ -125,11 +125,11 @@ SideCtx* side_ctx() {
   return &c;
 }
 
-// FP64 product for the U / V stream with the reduction cut into launches
-// of at most `chunk` (beta = 1 after the first): each workgroup then runs
-// for tens of microseconds, so a panel kernel on the main stream, which
-// needs most of a CU's LDS, finds a free CU quickly instead of waiting for
-// long side-stream workgroups to drain.
+// FP64 product for the U / V stream on 64 x 64 tiles with the reduction cut
+// into launches of at most `chunk` (beta = 1 after the first): each
+// workgroup then runs for tens of microseconds, so a panel kernel on the
+// main stream, which needs most of a CU's LDS, finds a free CU quickly
+// instead of waiting for long side-stream workgroups to drain.
 constexpr int kSideChunk = 256;     // reduction chunk of the thin products W = X Vh
 constexpr int kSideChunkUpd = 256;  // and of the rank-b updates X -= W2 Vh^T
 hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha,
@@ -140,7 +140,7 @@ hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, doub
     const double* Ak = A + (ta ? (int64_t)k0 : (int64_t)k0 * lda);
     const double* Bk = B + (tb ? (int64_t)k0 * ldb : (int64_t)k0);
     const hipError_t e = gemm(st, PREC_FP64, ta, tb, M, N, kc, alpha, Ak, lda, Bk, ldb,
-                              k0 == 0 ? beta : 1.0, C, ldc, nullptr, 0);
+                              k0 == 0 ? beta : 1.0, C, ldc, nullptr, 0, true);
     if (e != hipSuccess) return e;
     if (K <= 0) break;
   }
