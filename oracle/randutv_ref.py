@@ -153,10 +153,12 @@ def randutv(A, b, q, G, *, form_u=True, form_v=True, k_stop=0, tol=0.0,
             small_svds=True):
     """[U, T, V, k] = randUTV(A, b, q) following Figure randUTV step by step.
 
-    A: m x n with m >= n.  G: m x (num_random_steps*b) packed Gaussian.
+    A: m x n (any shape).  G: m x (num_random_steps*b) packed Gaussian.
     Returns U (m x m or None), T (m x n), V (n x n or None), and k, the
     number of leading columns driven to triangular form (= min(m, n) unless
-    the factorization stopped early).
+    the factorization stopped early).  With m < n the last step takes the
+    SVD of the wide block row through an LQ of its rows (Remark on the case
+    m < n, Section 5.2).
 
     small_svds=False skips the b x b SVD of each randomized step (the
     diagonal blocks are then left as the R factors of the panel QR).  This is
@@ -164,8 +166,6 @@ def randutv(A, b, q, G, *, form_u=True, form_v=True, k_stop=0, tol=0.0,
     """
     A = np.asarray(A)
     m, n = A.shape
-    if m < n:
-        raise ValueError("randutv oracle: m >= n required")
     if b < 1 or q < 0:
         raise ValueError("randutv oracle: b >= 1 and q >= 0 required")
     dt = np.result_type(A.dtype, np.float64)
@@ -221,6 +221,24 @@ def randutv(A, b, q, G, *, form_u=True, form_v=True, k_stop=0, tol=0.0,
             # (Remark on the economic SVD of a tall matrix, Section 4.4).
             X = np.array(T[r0:, r0:])
             p, c = X.shape
+            if p < c:
+                # Fewer rows than columns (Remark on the case m < n): an
+                # unpivoted QR of the rows, X^T = H [R; 0], so X = [R^T, 0] H^T,
+                # then the SVD of the p x p lower-triangular L = R^T.  The right
+                # transform is H diag(Vs, I): its reflectors act on the
+                # columns of T (all rows above the block) and of V.
+                reflV, R = house_qr(X.T)
+                Us, D, Vs = small_svd(R[:p, :p].T)
+                apply_right(T[:r0, r0:], reflV)
+                T[:r0, r0:r0 + p] = T[:r0, r0:r0 + p] @ Vs
+                if form_v:
+                    apply_right(V[:, r0:], reflV)
+                    V[:, r0:r0 + p] = V[:, r0:r0 + p] @ Vs
+                if form_u:
+                    U[:, r0:] = U[:, r0:] @ Us
+                T[r0:, r0:] = 0.0
+                T[r0:, r0:r0 + p] = np.diag(D)
+                continue
             if p == c:
                 Us, D, Vs = small_svd(X)
                 if form_u:

@@ -178,14 +178,16 @@ def test_b_ge_n_is_exact_svd():
     branch, so diag(T) are the singular values (tall input: economic QR+SVD,
     Remark on the economic SVD)."""
     rng = np.random.default_rng(12)
-    for (m, n) in [(20, 20), (35, 12)]:
+    for (m, n) in [(20, 20), (35, 12), (12, 35)]:
         A = rng.standard_normal((m, n))
         G = np.zeros((m, 0))
         U, T, V, k = ref.randutv(A, 32, 1, G)
         s = np.linalg.svd(A, compute_uv=False)
         np.testing.assert_allclose(np.diag(T), s, rtol=1e-14 * 10, atol=1e-15)
         _check_utv(A, U, T, V, k, 32)
+        assert k == min(m, n)
         assert np.all(T[n:, :] == 0.0)
+        assert np.all(T[:, m:] == 0.0)  # wide input: [diag(sigma), 0] (Remark on m < n)
 
 
 def test_rank_le_b_captured_in_first_block():
@@ -229,7 +231,8 @@ def _dense_lapack_randutv(A, b, q, G):
     """Independent dense re-implementation of the blocked method with LAPACK
     primitives and explicit m x m / n x n orthogonal factors (the O(n^4)
     style of Figure randUTVmatlab, with the economic left transform of the
-    Remark on tall SVDs so that complements are Householder ones)."""
+    Remark on tall SVDs so that complements are Householder ones, and the
+    LQ of the Remark on the case m < n for a wide last block)."""
     m, n = A.shape
     T = A.copy()
     U = np.eye(m)
@@ -257,6 +260,20 @@ def _dense_lapack_randutv(A, b, q, G):
             UU[:, :b] = Uq[:, :b] @ Us
             VV = Vq.copy()
             VV[:, :b] = Vq[:, :b] @ Vs
+        elif Mi < Ni:
+            # Wide last block: LQ of the rows via LAPACK's QR of X^T, then the
+            # SVD of the Mi x Mi lower-triangular factor (signs normalised on
+            # that SVD's right singular vectors).
+            Qt, Rt = scipy.linalg.qr(X.T, mode="full")
+            Us, D, Vlt = np.linalg.svd(Rt[:Mi, :Mi].T)
+            Vl = Vlt.T
+            for j in range(D.size):
+                if Vl[np.argmax(np.abs(Vl[:, j])), j] < 0:
+                    Vl[:, j] *= -1
+                    Us[:, j] *= -1
+            VV = Qt.copy()
+            VV[:, :Mi] = Qt[:, :Mi] @ Vl
+            UU = Us
         else:
             Uf, D, Vft = np.linalg.svd(X, full_matrices=True)
             Vs = Vft.T
@@ -287,6 +304,26 @@ def test_oracle_matches_dense_lapack_version(shape, b, q):
     np.testing.assert_allclose(V, V2, atol=1e-10)
     np.testing.assert_allclose(U[:, :n], U2[:, :n], atol=1e-10)
     _check_utv(A, U, T, V, k, b)
+
+
+@pytest.mark.parametrize("shape,b,q", [((41, 57), 8, 2), ((37, 40), 6, 0), ((30, 90), 8, 1)])
+def test_wide_matches_dense_lapack_version(shape, b, q):
+    """m < n (Remark on the case m < n): the first s-1 steps as for tall
+    input, the last one an LQ of the block row followed by the small SVD.
+    Against the dense LAPACK-primitive version: U, and the first m columns
+    of T and V (the columns beyond are a Householder complement in one route
+    and LAPACK's in the other, so not comparable); plus the UTV invariants."""
+    m, n = shape
+    A = wl.planted(m, n, np.exp(-np.arange(1, m + 1) / 10.0), seed=8)
+    G = wl.gaussian_g(m, n, b, seed=1)
+    U, T, V, k = ref.randutv(A, b, q, G)
+    assert k == m
+    U2, T2, V2 = _dense_lapack_randutv(A, b, q, G)
+    np.testing.assert_allclose(T[:, :m], T2[:, :m], atol=1e-11)
+    np.testing.assert_allclose(V[:, :m], V2[:, :m], atol=1e-10)
+    np.testing.assert_allclose(U, U2, atol=1e-10)
+    _check_utv(A, U, T, V, k, b)
+    assert np.all(np.tril(T, -1) == 0.0)
 
 
 def test_c1_invariants_and_logdet_golden():
