@@ -196,6 +196,39 @@ def early_stop_run(B, torch, wl):
         return {"error": repr(e)}
 
 
+def wide_run(B, torch, wl):
+    """4000 x 8000 (m < n: the last step is the LQ of the block row),
+    sigma_j = exp(-j/400), b = 256, q = 1, U and V formed: time per
+    factorization on the FP64 and the headline split path, with the
+    residual of each."""
+    import numpy as np
+    try:
+        m, n, b, q = 4000, 8000, 256, 1
+        sig = np.exp(-np.arange(1, m + 1) / 400.0)
+        A = wl.planted(m, n, sig, seed=0)
+        dA = B.colmajor(A)
+        dG = B.colmajor(wl.gaussian_g(m, n, b, seed=1))
+        del A
+        T = B.empty_colmajor(m, n)
+        U = B.empty_colmajor(m, m)
+        V = B.empty_colmajor(n, n)
+        out = {"config": "4000x8000, sigma_j=exp(-j/400), b=256, q=1, U and V formed"}
+        for prec in ("fp64", "bf16x3_fp32"):
+            work = B.workspace(B.workspace_size(m, n, b, q, prec, True, True))
+
+            def step():
+                T.copy_(dA)
+                B.randutv_factor(T, dG, b, q, U=U, V=V, prec=prec, work=work, sync=False)
+
+            ms = _timed(torch, step, 3)
+            res = (torch.linalg.norm(dA - U @ (T @ V.T)) / torch.linalg.norm(dA)).item()
+            log(f"wide 4000x8000 [{prec}]: {ms:.2f} ms, residual {res:.2e}")
+            out[prec] = {"ms": ms, "residual": res}
+        return out
+    except Exception as e:  # reported, never fatal to the headline line
+        return {"error": repr(e)}
+
+
 def approx_run(B, torch, wl):
     """2048 x 1024, sigma_j = exp(-j/100), b = 64, q = 1, k = 128: forward
     A_k and the hand-written backward of L = ||A_k - B||^2, FP64 storage,
@@ -336,6 +369,7 @@ def main():
     if not args.no_extra:
         out["early_stop_20000x5000"] = early_stop_run(B, torch, wl)
         out["approx_2048x1024"] = approx_run(B, torch, wl)
+        out["wide_4000x8000"] = wide_run(B, torch, wl)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_n}x{args.cpu_n} sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, b, q)

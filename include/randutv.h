@@ -16,8 +16,9 @@
  *    unimplemented case; RANDUTV_E_WORKSPACE if the workspace is too small;
  *    RANDUTV_E_SYNC if a cross-workgroup wait exceeded its spin limit;
  *    RANDUTV_E_HIP - (int)hipError for HIP runtime failures.
- *  - Only m >= n is supported (the paper's setting for an upper triangular T,
- *    Section 5); m < n returns RANDUTV_E_UNSUPPORTED.
+ *  - Any m, n >= 1 for the factorization (m < n: the last step is the LQ of
+ *    the wide block row, the paper's Remark on the case m < n in Section
+ *    5.2); the truncated approximation takes m >= n.
  */
 #ifndef RANDUTV_H
 #define RANDUTV_H
@@ -76,8 +77,11 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
  * 5.2; single step Section 4; the economic final SVD of the Remark in
  * Section 4.4).
  *
- *  1  m, n     rows and columns of A, m >= n >= 1.
- *  2  b        block size, 1 <= b <= 256.  m <= 32768.
+ *  1  m, n     rows and columns of A, m, n >= 1.  With m < n the first
+ *              steps are as for tall input and the last one takes an LQ of the
+ *              block row T(I2, [J2,J3]) (the QR of its transpose), then the SVD
+ *              of its lower-triangular factor; T is upper trapezoidal.
+ *  2  b        block size, 1 <= b <= 256.  max(m, n) <= 32768.
  *  3  q        power-iteration count, 0 <= q <= 16.
  *  4  T, ldt   in: A (m x n).  out: the middle factor T, upper triangular in
  *              the first k columns, with exact zeros below the diagonal and

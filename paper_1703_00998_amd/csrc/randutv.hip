@@ -64,8 +64,8 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
   L.Uh2 = take(mb * d);
   L.W = take(mb * d);
   L.W2 = take(mb * d);
-  L.Ws = take(mb * d);
-  L.W2s = take(mb * d);
+  L.Ws = take(std::max(mb, nb) * d);   // U / V stream products, leading dimension max(m, n)
+  L.W2s = take(std::max(mb, nb) * d);
   L.C = take(nb * d);
   L.C2 = take(nb * d);
   L.TwV = take(bb * d);
@@ -147,6 +147,21 @@ hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, doub
   return hipSuccess;
 }
 
+inline int grid_blocks(int64_t total) { return (int)std::min<int64_t>((total + 255) / 256, 4096); }
+
+// B = A^T for the M x N matrix A (B is N x M).  Used once per factorization
+// (the wide last block), so a plain strided copy.
+__global__ void k_transpose(int M, int N, const double* __restrict__ A, int64_t lda,
+                            double* __restrict__ Bt, int64_t ldb) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % M);
+    const int64_t j = idx / M;
+    Bt[j + (int64_t)i * ldb] = A[i + j * lda];
+  }
+}
+
 __global__ void k_set_ints(int* p, int count, int v, int last) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = (i == count - 1) ? last : v;
 }
@@ -181,7 +196,6 @@ int64_t randutv_g_cols(int64_t m, int64_t n, int64_t b) {
 int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, unsigned flags,
                            size_t* bytes) {
   if (n < 1 || m < 1) return -1;
-  if (m < n) return RANDUTV_E_UNSUPPORTED;
   if (b < 1 || b > kMaxB) return -3;
   if (q < 0 || q > 16) return -4;
   if (prec < 0 || prec > 3) return -5;
@@ -220,8 +234,8 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
                 double tol, int prec, unsigned flags, void* work, size_t work_bytes,
                 int64_t* k_out, void* stream, const ApproxTape* tape) {
   if (m < 1 || n < 1) return -1;
-  if (m < n) return RANDUTV_E_UNSUPPORTED;
-  if (m > kMaxPanelRows || m * n > ((int64_t)1 << 40)) return RANDUTV_E_UNSUPPORTED;
+  if (m < n && tape) return RANDUTV_E_UNSUPPORTED;  // the approximation takes m >= n
+  if (std::max(m, n) > kMaxPanelRows || m * n > ((int64_t)1 << 40)) return RANDUTV_E_UNSUPPORTED;
   if (b < 1 || b > kMaxB) return -2;
   if (q < 0 || q > 16) return -3;
   if (!T || ldt < m) return -4;
@@ -258,6 +272,7 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
   const Prec pu = prec == kPrecMixed ? PREC_FP32 : (Prec)prec;
   const size_t se = L.split_elems;
   const int M = (int)m, N = (int)n, B = (int)b;
+  const int MN = std::max(M, N);  // leading dimension of the U / V stream products
 
   double* const VhS[2] = {dp(L.Vh), dp(L.Vh2)};
   double* const UhS[2] = {dp(L.Uh), dp(L.Uh2)};
@@ -299,7 +314,7 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
   }
 
   std::vector<int> widths;
-  int64_t k_done = n;
+  int64_t k_done = std::min(m, n);
   for (int64_t i = 0; i < s; ++i) {
     const int r0 = (int)(i * b);
     const int Mi = M - r0, Ni = N - r0;
@@ -334,9 +349,9 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
       if (formV) {  // V(:, J) = V(:, J) Vq, on the U / V stream
         double* VJ = V + (int64_t)r0 * ldv;
         HIPCHK(to_side(0 + sl));
-        HIPCHK(gemm_side(ss, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, M, kSideChunk));
-        HIPCHK(gemm(ss, PREC_FP64, false, false, N, B, B, 1.0, Ws, M, TwV, B, 0.0, W2s, M, nullptr, 0));
-        HIPCHK(gemm_side(ss, false, true, N, Ni, B, -1.0, W2s, M, Vh, N, 1.0, VJ, ldv, kSideChunkUpd));
+        HIPCHK(gemm_side(ss, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, MN, kSideChunk));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, N, B, B, 1.0, Ws, MN, TwV, B, 0.0, W2s, MN, nullptr, 0));
+        HIPCHK(gemm_side(ss, false, true, N, Ni, B, -1.0, W2s, MN, Vh, N, 1.0, VJ, ldv, kSideChunkUpd));
         HIPCHK(side_done(4 + sl, &vpend[sl]));
       }
       // [Uq, R] = qr(T([I2,I3], J2))
@@ -353,9 +368,9 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
       if (formU) {  // on the U / V stream
         double* UI = U + (int64_t)r0 * ldu;
         HIPCHK(to_side(2 + sl));
-        HIPCHK(gemm_side(ss, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, M, kSideChunk));
-        HIPCHK(gemm(ss, PREC_FP64, false, false, M, B, B, 1.0, Ws, M, TwU, B, 0.0, W2s, M, nullptr, 0));
-        HIPCHK(gemm_side(ss, false, true, M, Mi, B, -1.0, W2s, M, Uh, M, 1.0, UI, ldu, kSideChunkUpd));
+        HIPCHK(gemm_side(ss, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, kSideChunk));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, M, B, B, 1.0, Ws, MN, TwU, B, 0.0, W2s, MN, nullptr, 0));
+        HIPCHK(gemm_side(ss, false, true, M, Mi, B, -1.0, W2s, MN, Uh, M, 1.0, UI, ldu, kSideChunkUpd));
         HIPCHK(side_done(6 + sl, &upend[sl]));
       }
       // T([I2,I3], J2) = [R; 0]; R moves to the stash, the diagonal block is
@@ -374,6 +389,39 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
         k_done = r0 + B;
         break;
       }
+    } else if (Mi < Ni) {
+      // Last block with fewer rows than columns (the paper's remark on the
+      // case m < n): an LQ of the block row T(I2, [J2,J3]) as the Householder
+      // QR of its transpose (copied into Y), so T(I2, J) = [L, 0] H^T with
+      // L = R^T.  H acts from the right on the rows above the block and on V;
+      // L goes to the stash for the batched SVD, whose right singular vectors
+      // fold into the first Mi columns of J as for any other block.
+      const int c = Mi;
+      double* TJ = T + (int64_t)r0 * ldt;
+      hipLaunchKernelGGL(k_transpose, dim3(grid_blocks((int64_t)Mi * Ni)), dim3(256), 0, st, Mi,
+                         Ni, X, ldt, Y, (int64_t)N);
+      HIPCHK(hipGetLastError());
+      HIPCHK(reclaim(4 + sl, vpend[sl]));
+      HIPCHK(panel_qr_hr(st, Ni, c, Y, N, Vh, N, Ftmp, c, tauV, TwV, B, hw, pw, split, se));
+      hipLaunchKernelGGL(k_transpose, dim3(grid_blocks((int64_t)c * c)), dim3(256), 0, st, c, c,
+                         Ftmp, (int64_t)c, RU, (int64_t)B);
+      HIPCHK(hipGetLastError());
+      if (r0 > 0) {  // T(I1, J) = T(I1, J) H
+        HIPCHK(gemm(st, PREC_FP64, false, false, r0, c, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
+        HIPCHK(gemm(st, PREC_FP64, false, false, r0, c, c, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
+        HIPCHK(gemm(st, PREC_FP64, false, true, r0, Ni, c, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
+      }
+      if (formV) {  // V(:, J) = V(:, J) H, on the U / V stream
+        double* VJ = V + (int64_t)r0 * ldv;
+        HIPCHK(to_side(0 + sl));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, N, c, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, MN, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, N, c, c, 1.0, Ws, MN, TwV, B, 0.0, W2s, MN, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, true, N, Ni, c, -1.0, W2s, MN, Vh, N, 1.0, VJ, ldv, nullptr, 0));
+        HIPCHK(side_done(4 + sl, &vpend[sl]));
+      }
+      HIPCHK(set_zero(st, Mi, Ni, X, ldt));
+      widths.push_back(c);
+      k_done = M;
     } else {
       // Last block: economic SVD via Householder QR of T([I2,I3],[J2,J3]).
       const int c = Ni;
@@ -383,9 +431,9 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
       if (formU) {
         double* UI = U + (int64_t)r0 * ldu;
         HIPCHK(to_side(2 + sl));
-        HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, M, nullptr, 0));
-        HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, c, 1.0, Ws, M, TwU, B, 0.0, W2s, M, nullptr, 0));
-        HIPCHK(gemm(ss, PREC_FP64, false, true, M, Mi, c, -1.0, W2s, M, Uh, M, 1.0, UI, ldu, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, c, 1.0, Ws, MN, TwU, B, 0.0, W2s, MN, nullptr, 0));
+        HIPCHK(gemm(ss, PREC_FP64, false, true, M, Mi, c, -1.0, W2s, MN, Uh, M, 1.0, UI, ldu, nullptr, 0));
         HIPCHK(side_done(6 + sl, &upend[sl]));
       }
       HIPCHK(set_zero(st, Mi, c, X, ldt));

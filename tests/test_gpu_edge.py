@@ -158,3 +158,59 @@ def test_early_stop_boundaries(B, k_stop, tol, expect):
     assert k == ko == expect
     np.testing.assert_allclose(_np(T)[:k, :k], To[:k, :k], rtol=0, atol=1e-10 * np.linalg.norm(A))
     assert _residual(A, U, T, V) <= 1e-13
+
+
+@pytest.mark.parametrize("shape,b,q", [((80, 120), 16, 1), ((200, 1000), 32, 1), ((64, 100), 64, 1),
+                                       ((130, 257), 32, 2), ((33, 40), 8, 0), ((1, 50), 8, 1)])
+def test_wide_input_matches_oracle(B, shape, b, q):
+    """m < n (the paper's Remark on the case m < n): the last step is an LQ of
+    the block row, taken as the Householder QR of its transpose, then the
+    SVD of the lower-triangular factor.  T, U, V elementwise against the
+    oracle (same Householder convention, so the complements agree too) and
+    the UTV invariants."""
+    m, n = shape
+    print(f"wide factor m={m} n={n} b={b} q={q}", flush=True)
+    sig = np.exp(-np.arange(1, m + 1) / max(2.0 * b, 4.0))
+    A = wl.planted(m, n, sig, seed=0)
+    G = wl.gaussian_g(m, n, b, seed=1)
+    Uo, To, Vo, ko = ref.randutv(A, b, q, G)
+    U, T, V, k = _factor(B, A, b, q, G)
+    assert k == ko == m
+    nA = np.linalg.norm(A)
+    np.testing.assert_allclose(_np(T), To, rtol=0, atol=1e-10 * nA)
+    np.testing.assert_allclose(_np(U), Uo, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(_np(V), Vo, rtol=0, atol=1e-9)
+    assert _residual(A, U, T, V) <= 1e-13
+    assert _orth(U) <= 1e-13 * math.sqrt(m) * 10 and _orth(V) <= 1e-13 * math.sqrt(n) * 10
+    assert np.all(np.tril(_np(T), -1) == 0.0)
+
+
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-6), ("bf16x3_fp32", 1e-6)])
+def test_wide_input_split_paths(B, prec, bound):
+    """A wide 600 x 1000 matrix on the split-precision paths: residual within
+    the path's bound, U and V orthogonal to FP64 rounding, T upper
+    trapezoidal."""
+    m, n, b, q = 600, 1000, 64, 1
+    sig = np.exp(-np.arange(1, m + 1) / 150.0)
+    A = wl.planted(m, n, sig, seed=0)
+    G = wl.gaussian_g(m, n, b, seed=1)
+    print(f"wide split path {prec}", flush=True)
+    U, T, V, k = _factor(B, A, b, q, G, prec=prec)
+    assert k == m
+    assert _residual(A, U, T, V) <= bound
+    assert _orth(U) <= 1e-12 * math.sqrt(m) and _orth(V) <= 1e-12 * math.sqrt(n)
+    assert np.all(np.tril(_np(T), -1) == 0.0)
+
+
+def test_wide_input_early_stop(B):
+    """Early stop on a wide input (k_stop = 2b < m): the reduced part agrees
+    with the oracle stopped the same way."""
+    m, n, b, q = 150, 400, 32, 1
+    sig = np.exp(-np.arange(1, m + 1) / 20.0)
+    A = wl.planted(m, n, sig, seed=0)
+    G = wl.gaussian_g(m, n, b, seed=1)
+    Uo, To, Vo, ko = ref.randutv(A, b, q, G, k_stop=2 * b)
+    U, T, V, k = _factor(B, A, b, q, G, k_stop=2 * b)
+    assert k == ko == 2 * b
+    np.testing.assert_allclose(_np(T)[:k, :k], To[:k, :k], rtol=0, atol=1e-10 * np.linalg.norm(A))
+    assert _residual(A, U, T, V) <= 1e-13
