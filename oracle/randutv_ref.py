@@ -19,7 +19,9 @@ design notes of the repository):
     sign-normalised so that the largest-magnitude entry of v_j is positive
     (ties: lowest index) (`small_svd`).
   * Random matrices: step i (0-based) uses the leading m - i*b rows of column
-    block i of one packed m x (s_r*b) Gaussian matrix G (`g_slab`).
+    block i of one packed m x (s_r*(b+p)) Gaussian matrix G (`g_slab`).
+  * Over-sampling (p > 0): the b dominant left singular vectors of the
+    extended sampling matrix, signs normalised as for the small SVDs.
   * "qr(Y)" is unpivoted Householder QR (Section 4.3; Figure randUTV).
   * The right transform touches all m rows of T (Figure randUTV:
     T(:,[J2,J3]) = T(:,[J2,J3]) V).
@@ -38,6 +40,7 @@ import numpy as np
 
 __all__ = [
     "householder", "house_qr", "apply_right", "apply_left", "small_svd",
+    "top_left_singular_vectors",
     "num_steps", "num_random_steps", "g_slab", "randutv", "approx",
     "approx_jvp", "flops_paper", "flops_uv",
 ]
@@ -141,19 +144,39 @@ def num_random_steps(m, n, b):
                if i * b + b < m and i * b + b < n)
 
 
-def g_slab(G, m, b, i):
-    """G_i: the leading m - i*b rows of column block i of the packed G."""
-    return G[: m - i * b, i * b:(i + 1) * b]
+def g_slab(G, m, b, i, p=0):
+    """G_i: the leading m - i*b rows of column block i (b + p columns wide)
+    of the packed G."""
+    w = b + p
+    return G[: m - i * b, i * w:(i + 1) * w]
+
+
+def top_left_singular_vectors(Y, b):
+    """The b dominant left singular vectors of the n_i x (b+p) matrix Y
+    (Appendix A.2, Figure stepUTVoversampling: [Z,~,~] = svd(Y,'econ'),
+    Z(:,1:b)), each pair (z_j, w_j) sign-normalised like `small_svd` (the
+    largest-magnitude entry of the right singular vector w_j positive)."""
+    Z, _, Wt = np.linalg.svd(Y, full_matrices=False)
+    Z = Z[:, :b].copy()
+    for j in range(b):
+        idx = int(np.argmax(np.abs(Wt[j, :])))
+        if Wt[j, idx] < 0.0:
+            Z[:, j] = -Z[:, j]
+    return Z
 
 
 # --------------------------------------------------------------------------
 # Figure randUTV (Section 5.2): the blocked algorithm.
 # --------------------------------------------------------------------------
-def randutv(A, b, q, G, *, form_u=True, form_v=True, k_stop=0, tol=0.0,
+def randutv(A, b, q, G, *, p=0, form_u=True, form_v=True, k_stop=0, tol=0.0,
             small_svds=True):
     """[U, T, V, k] = randUTV(A, b, q) following Figure randUTV step by step.
 
-    A: m x n (any shape).  G: m x (num_random_steps*b) packed Gaussian.
+    A: m x n (any shape).  G: m x (num_random_steps*(b+p)) packed Gaussian.
+    p > 0 over-samples (Remark "Oversampling" in Section 5.3, Appendix A.2,
+    Figure stepUTVoversampling): each step draws b+p samples, and the
+    Householder QR is taken of the b dominant left singular vectors of the
+    extended sampling matrix instead of the sampling matrix itself.
     Returns U (m x m or None), T (m x n), V (n x n or None), and k, the
     number of leading columns driven to triangular form (= min(m, n) unless
     the factorization stopped early).  With m < n the last step takes the
@@ -166,8 +189,8 @@ def randutv(A, b, q, G, *, form_u=True, form_v=True, k_stop=0, tol=0.0,
     """
     A = np.asarray(A)
     m, n = A.shape
-    if b < 1 or q < 0:
-        raise ValueError("randutv oracle: b >= 1 and q >= 0 required")
+    if b < 1 or q < 0 or p < 0:
+        raise ValueError("randutv oracle: b >= 1, q >= 0 and p >= 0 required")
     dt = np.result_type(A.dtype, np.float64)
     T = np.array(A, dtype=dt, copy=True)
     U = np.eye(m, dtype=dt) if form_u else None
@@ -182,10 +205,12 @@ def randutv(A, b, q, G, *, form_u=True, form_v=True, k_stop=0, tol=0.0,
         if r1 < m and c1 < n:
             # Sampling matrix Y = (X^T X)^q X^T G with X = T([I2,I3],[J2,J3]).
             X = T[r0:, r0:]
-            Gi = g_slab(G, m, b, i)
+            Gi = g_slab(G, m, b, i, p)
             Y = X.T @ Gi
             for _ in range(q):
                 Y = X.T @ (X @ Y)
+            if p > 0:
+                Y = top_left_singular_vectors(Y, b)
             # [Vq, ~] = qr(Y);  T(:,[J2,J3]) = T(:,[J2,J3]) Vq; V likewise.
             reflV, _ = house_qr(Y)
             apply_right(T[:, r0:], reflV)

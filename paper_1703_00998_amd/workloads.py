@@ -38,17 +38,17 @@ def planted(m, n, sigma, seed=0):
     return np.asfortranarray((X * sigma) @ Y.T)
 
 
-def g_cols(m, n, b):
-    """Columns of the packed Gaussian: b per step whose I3 and J3 are both
-    nonempty (m >= n: ceil(n/b) - 1 such steps)."""
+def g_cols(m, n, b, p=0):
+    """Columns of the packed Gaussian: b + p per step whose I3 and J3 are
+    both nonempty (m >= n: ceil(n/b) - 1 such steps)."""
     s = min(-(-m // b), -(-n // b))
-    return b * sum(1 for i in range(s) if i * b + b < m and i * b + b < n)
+    return (b + p) * sum(1 for i in range(s) if i * b + b < m and i * b + b < n)
 
 
-def gaussian_g(m, n, b, seed=1, cols=None):
-    """Packed N(0,1) matrix G, m x g_cols(m,n,b); step i uses the leading
-    m - i*b rows of column block i."""
-    c = g_cols(m, n, b) if cols is None else cols
+def gaussian_g(m, n, b, seed=1, cols=None, p=0):
+    """Packed N(0,1) matrix G, m x g_cols(m,n,b,p); step i uses the leading
+    m - i*b rows of column block i (b + p columns wide)."""
+    c = g_cols(m, n, b, p) if cols is None else cols
     rng = np.random.default_rng(seed)
     return np.asfortranarray(rng.standard_normal((m, c)))
 

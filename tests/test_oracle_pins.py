@@ -227,7 +227,7 @@ def test_theorem_step_one_identities():
     assert np.linalg.norm(A - U @ T @ V.T) <= 1e-13 * np.linalg.norm(A)
 
 
-def _dense_lapack_randutv(A, b, q, G):
+def _dense_lapack_randutv(A, b, q, G, p=0):
     """Independent dense re-implementation of the blocked method with LAPACK
     primitives and explicit m x m / n x n orthogonal factors (the O(n^4)
     style of Figure randUTVmatlab, with the economic left transform of the
@@ -243,10 +243,16 @@ def _dense_lapack_randutv(A, b, q, G):
         X = T[r0:, r0:]
         Mi, Ni = X.shape
         if r0 + b < m and r0 + b < n:
-            Gi = G[:Mi, i * b:(i + 1) * b]
+            Gi = G[:Mi, i * (b + p):(i + 1) * (b + p)]
             Y = X.T @ Gi
             for _ in range(q):
                 Y = X.T @ (X @ Y)
+            if p > 0:  # dominant b left singular vectors (signs as for the small SVDs)
+                Zy, _, Wyt = scipy.linalg.svd(Y, full_matrices=False, lapack_driver="gesvd")
+                for j in range(b):
+                    if Wyt[j, np.argmax(np.abs(Wyt[j, :]))] < 0:
+                        Zy[:, j] *= -1
+                Y = Zy[:, :b]
             Vq, _ = scipy.linalg.qr(Y, mode="full")
             XV = X @ Vq
             Uq, R = scipy.linalg.qr(XV[:, :b], mode="full")
@@ -324,6 +330,63 @@ def test_wide_matches_dense_lapack_version(shape, b, q):
     np.testing.assert_allclose(U, U2, atol=1e-10)
     _check_utv(A, U, T, V, k, b)
     assert np.all(np.tril(T, -1) == 0.0)
+
+
+@pytest.mark.parametrize("shape,b,q,p", [((48, 40), 8, 1, 4), ((60, 60), 8, 2, 8), ((40, 56), 8, 0, 3)])
+def test_oversampling_matches_dense_lapack_version(shape, b, q, p):
+    """Over-sampling (Appendix A.2, Figure stepUTVoversampling): against the
+    dense LAPACK-primitive version (LAPACK's gesvd for the extended sample's
+    singular vectors, LAPACK QR for the reflectors): T, V and the first
+    min(m, n) columns of U elementwise, and the UTV invariants."""
+    m, n = shape
+    A = wl.planted(m, n, np.exp(-np.arange(1, min(m, n) + 1) / 10.0), seed=8)
+    G = wl.gaussian_g(m, n, b, seed=1, p=p)
+    U, T, V, k = ref.randutv(A, b, q, G, p=p)
+    U2, T2, V2 = _dense_lapack_randutv(A, b, q, G, p)
+    r = min(m, n)
+    np.testing.assert_allclose(T[:, :r], T2[:, :r], atol=1e-11)
+    np.testing.assert_allclose(V[:, :r], V2[:, :r], atol=1e-10)
+    np.testing.assert_allclose(U[:, :r], U2[:, :r], atol=1e-10)
+    _check_utv(A, U, T, V, k, b)
+
+
+def test_oversampling_step_one_identities():
+    """Theorem (Section 5.3) with the over-sampled basis: after one step,
+    ||T(:, b:)||_F = ||A - A Q Q^T||_F and diag(T11) = sigma(A Q) for Q an
+    orthonormal basis of the b dominant left singular vectors of the extended
+    sample (A^T A)^q A^T G_1 (b + p columns), here from numpy's QR of those
+    vectors; and the captured norm is no worse than the optimal rank-b one
+    (Eckart-Young)."""
+    m, n, b, q, p = 50, 40, 8, 1, 5
+    A = wl.planted(m, n, np.exp(-np.arange(1, 41) / 6.0), seed=2)
+    G = wl.gaussian_g(m, n, b, seed=1, p=p)
+    U, T, V, k = ref.randutv(A, b, q, G, p=p, k_stop=b)
+    assert k == b
+    Y = A.T @ G[:, :b + p]
+    for _ in range(q):
+        Y = A.T @ (A @ Y)
+    Zy, _, _ = np.linalg.svd(Y, full_matrices=False)
+    Q, _ = np.linalg.qr(Zy[:, :b])
+    e1 = np.linalg.norm(A - A @ Q @ Q.T)
+    assert abs(np.linalg.norm(T[:, b:]) - e1) <= 1e-12 * e1 + 1e-14
+    np.testing.assert_allclose(np.diag(T)[:b], np.linalg.svd(A @ Q, compute_uv=False), rtol=1e-13)
+    sig = np.linalg.svd(A, compute_uv=False)
+    assert e1 >= np.sqrt(np.sum(sig[b:] ** 2)) * (1 - 1e-12)
+
+
+def test_oversampling_rank_le_b_equals_plain():
+    """rank(A) <= b: with or without over-sampling the first step's sample
+    spans the whole row space, so both capture A in the first block:
+    diag(T11) = sigma and the rest of T vanishes."""
+    m, n, b = 60, 40, 8
+    sig = np.array([5.0, 3.0, 2.0, 1.5, 1.0, 0.5])
+    A = wl.planted(m, n, sig, seed=9)
+    for p in (0, 6):
+        G = wl.gaussian_g(m, n, b, seed=1, p=p)
+        U, T, V, k = ref.randutv(A, b, 1, G, p=p)
+        np.testing.assert_allclose(np.diag(T)[:6], sig, rtol=1e-13)
+        assert np.linalg.norm(T[:, 6:]) <= 1e-13 * 5
+        _check_utv(A, U, T, V, k, b)
 
 
 def test_c1_invariants_and_logdet_golden():
