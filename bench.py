@@ -229,6 +229,46 @@ def wide_run(B, torch, wl):
         return {"error": repr(e)}
 
 
+def oversample_run(B, torch, wl):
+    """4000 x 4000, sigma_j = j^-1.5, b = 128, q = 1, U and V formed, with
+    p = 0 and p = 10 extra samples per step (Remark on over-sampling,
+    Section 5.3; Appendix A.2): time per factorization, and the Frobenius
+    error ||T(k:, k:)||_F of the rank-k truncation at every k = j*b,
+    divided by the optimal sqrt(sum_{i>k} sigma_i^2) (mean and max ratio)."""
+    import numpy as np
+    try:
+        A, sig = wl.config_matrix("c2_4000")
+        m, n, b, q = 4000, 4000, 128, 1
+        dA = B.colmajor(A)
+        del A
+        tail = np.sqrt(np.cumsum((sig ** 2)[::-1])[::-1])  # tail[k] = sqrt(sum_{i>=k} s_i^2)
+        ks = list(range(b, n, b))
+        T = B.empty_colmajor(m, n)
+        U = B.empty_colmajor(m, m)
+        V = B.empty_colmajor(n, n)
+        out = {"config": "4000x4000, sigma_j=j^-1.5, b=128, q=1, U and V formed"}
+        for p in (0, 10):
+            dG = B.colmajor(wl.gaussian_g(m, n, b, seed=1, p=p))
+            for prec in ("fp64", "bf16x3_fp32"):
+                work = B.workspace(B.workspace_size(m, n, b, q, prec, True, True, p=p))
+
+                def step():
+                    T.copy_(dA)
+                    B.randutv_factor(T, dG, b, q, U=U, V=V, prec=prec, work=work, sync=False,
+                                     p=p)
+
+                ms = _timed(torch, step, 3)
+                res = (torch.linalg.norm(dA - U @ (T @ V.T)) / torch.linalg.norm(dA)).item()
+                ratios = np.array([torch.linalg.norm(T[k:, k:]).item() / tail[k] for k in ks])
+                r = {"ms": ms, "residual": res, "frob_err_ratio_mean": float(ratios.mean()),
+                     "frob_err_ratio_max": float(ratios.max())}
+                log(f"oversample p={p} [{prec}]: {r}")
+                out[f"p{p}_{prec}"] = r
+        return out
+    except Exception as e:  # reported, never fatal to the headline line
+        return {"error": repr(e)}
+
+
 def approx_run(B, torch, wl):
     """2048 x 1024, sigma_j = exp(-j/100), b = 64, q = 1, k = 128: forward
     A_k and the hand-written backward of L = ||A_k - B||^2, FP64 storage,
@@ -370,6 +410,7 @@ def main():
         out["early_stop_20000x5000"] = early_stop_run(B, torch, wl)
         out["approx_2048x1024"] = approx_run(B, torch, wl)
         out["wide_4000x8000"] = wide_run(B, torch, wl)
+        out["oversample_4000"] = oversample_run(B, torch, wl)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_n}x{args.cpu_n} sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, b, q)

@@ -129,6 +129,40 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q,
                    void* work, size_t work_bytes,
                    int64_t* k_out, void* stream);
 
+/*
+ * Over-sampled variants (Remark on over-sampling, Section 5.3; Appendix A.2,
+ * the over-sampled step): each randomized step draws b + p samples,
+ * Y = (X^T X)^q X^T G_i with G_i of b + p columns, and the Householder QR is
+ * taken of the b dominant left singular vectors of Y instead of Y itself.
+ * Each such vector's sign is fixed by its right singular vector, whose
+ * largest-magnitude entry is made positive (the rule of the small SVDs).
+ * p = 0 gives randutv_g_cols / randutv_workspace_size / randutv_factor.
+ *
+ * randutv_g_cols_p: (b + p) * randutv_random_steps(); -1 for invalid sizes.
+ *   Randomized step i uses G(0:m-i*b-1, i*(b+p):(i+1)*(b+p)-1).
+ * randutv_workspace_size_p: as randutv_workspace_size; status -4 when
+ *   p < 0 or b + p > 256 (the later arguments' codes shift by one).
+ * randutv_factor_p: arguments and results as randutv_factor with p after b;
+ *   0 <= p and b + p <= 256, else status -13.  The SVD of each step's
+ *   extended sample runs on the device between the sampling products and
+ *   the QR; when k_out is non-NULL, a non-converged one reports status 1
+ *   like a non-converged small SVD.  Each such SVD waits on the host for
+ *   its convergence test, so the call does not run fully ahead of the
+ *   stream.
+ */
+int64_t randutv_g_cols_p(int64_t m, int64_t n, int64_t b, int64_t p);
+int randutv_workspace_size_p(int64_t m, int64_t n, int64_t b, int64_t p, int q,
+                             int prec, unsigned flags, size_t* bytes);
+int randutv_factor_p(int64_t m, int64_t n, int64_t b, int64_t p, int q,
+                     double* T, int64_t ldt,
+                     const double* G, int64_t ldg,
+                     double* U, int64_t ldu,
+                     double* V, int64_t ldv,
+                     int64_t k_stop, double tol,
+                     int prec, unsigned flags,
+                     void* work, size_t work_bytes,
+                     int64_t* k_out, void* stream);
+
 /* ---- Building blocks of one step (exported for testing and reuse) ---- */
 
 /* Truncated approximation (Section 6.2, eq. Ak_randUTV; Theorem of Section

@@ -49,6 +49,14 @@ def lib():
     L.randutv_factor.argtypes = [i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, i64,
                                  i64, dbl, i32, u32, vp, sz, ctypes.POINTER(i64), vp]
     L.randutv_factor.restype = i32
+    L.randutv_g_cols_p.argtypes = [i64, i64, i64, i64]
+    L.randutv_g_cols_p.restype = i64
+    L.randutv_workspace_size_p.argtypes = [i64, i64, i64, i64, i32, i32, u32,
+                                           ctypes.POINTER(sz)]
+    L.randutv_workspace_size_p.restype = i32
+    L.randutv_factor_p.argtypes = [i64, i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, i64,
+                                   i64, dbl, i32, u32, vp, sz, ctypes.POINTER(i64), vp]
+    L.randutv_factor_p.restype = i32
     L.randutv_gemm.argtypes = [i32, i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl,
                                vp, i64, vp, sz, vp]
     L.randutv_gemm.restype = i32
@@ -87,7 +95,8 @@ def lib():
 
 
 EXPORTS = ["randutv_random_steps", "randutv_g_cols", "randutv_workspace_size",
-           "randutv_factor", "randutv_gemm", "randutv_panel_work_size", "randutv_panel_qr",
+           "randutv_factor", "randutv_g_cols_p", "randutv_workspace_size_p", "randutv_factor_p",
+           "randutv_gemm", "randutv_panel_work_size", "randutv_panel_qr",
            "randutv_small_svd_work_size", "randutv_small_svd", "randutv_strerror",
            "randutv_profile_begin", "randutv_profile_end", "randutv_profile_class_name",
            "randutv_approx_tape_size", "randutv_approx_work_size", "randutv_approx",
@@ -153,15 +162,21 @@ def random_steps(m, n, b):
     return int(lib().randutv_random_steps(m, n, b))
 
 
-def g_cols(m, n, b):
+def g_cols(m, n, b, p=0):
+    if p:
+        return int(lib().randutv_g_cols_p(m, n, b, p))
     return int(lib().randutv_g_cols(m, n, b))
 
 
-def workspace_size(m, n, b, q=1, prec="fp64", form_u=True, form_v=True):
+def workspace_size(m, n, b, q=1, prec="fp64", form_u=True, form_v=True, p=0):
     flags = (FORM_U if form_u else 0) | (FORM_V if form_v else 0)
     out = ctypes.c_size_t(0)
-    _check(lib().randutv_workspace_size(m, n, b, q, PREC[prec], flags, ctypes.byref(out)),
-           "randutv_workspace_size")
+    if p:
+        _check(lib().randutv_workspace_size_p(m, n, b, p, q, PREC[prec], flags,
+                                              ctypes.byref(out)), "randutv_workspace_size_p")
+    else:
+        _check(lib().randutv_workspace_size(m, n, b, q, PREC[prec], flags, ctypes.byref(out)),
+               "randutv_workspace_size")
     return int(out.value)
 
 
@@ -176,33 +191,42 @@ def _aligned_ptr(ws):
 
 
 def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", work=None,
-                   sync=True):
+                   sync=True, p=0):
     """In-place randUTV of T (m x n column-major FP64, overwritten by T).
 
-    U (m x m) and V (n x n) are written when given.  Returns k (the number of
-    leading columns reduced) when sync=True, else None (enqueue only).
+    U (m x m) and V (n x n) are written when given.  p > 0 over-samples
+    (randutv_factor_p; G then has b + p columns per randomized step).
+    Returns k (the number of leading columns reduced) when sync=True, else
+    None (enqueue only).
     """
     m, n = T.shape
     ldt = _ld(T, m)
-    gc = g_cols(m, n, b)
+    gc = g_cols(m, n, b, p)
     ldg = _ld(G, m) if (G is not None and G.numel() > 0) else max(m, 1)
     if gc > 0 and (G is None or G.shape[1] < gc):
         raise RandUTVError(f"G needs {gc} columns")
     ldu = _ld(U, m) if U is not None else m
     ldv = _ld(V, n) if V is not None else n
     flags = (FORM_U if U is not None else 0) | (FORM_V if V is not None else 0)
-    need = workspace_size(m, n, b, q, prec, U is not None, V is not None)
+    need = workspace_size(m, n, b, q, prec, U is not None, V is not None, p=p)
     if work is None:
         work = workspace(need, T.device)
     wp, wbytes = _aligned_ptr(work)
     if wbytes < need:
         raise RandUTVError("workspace too small")
     k = ctypes.c_int64(0)
-    st = lib().randutv_factor(
-        m, n, b, q, _ptr(T), ldt, _ptr(G) if gc > 0 else ctypes.c_void_p(0), ldg,
-        _ptr(U), ldu, _ptr(V), ldv, int(k_stop), float(tol), PREC[prec], flags, wp, wbytes,
-        ctypes.byref(k) if (sync or tol > 0) else None, _stream())
-    _check(st, "randutv_factor")
+    kp = ctypes.byref(k) if (sync or tol > 0) else None
+    gp = _ptr(G) if gc > 0 else ctypes.c_void_p(0)
+    if p:
+        st = lib().randutv_factor_p(
+            m, n, b, p, q, _ptr(T), ldt, gp, ldg, _ptr(U), ldu, _ptr(V), ldv, int(k_stop),
+            float(tol), PREC[prec], flags, wp, wbytes, kp, _stream())
+        _check(st, "randutv_factor_p")
+    else:
+        st = lib().randutv_factor(
+            m, n, b, q, _ptr(T), ldt, gp, ldg, _ptr(U), ldu, _ptr(V), ldv, int(k_stop),
+            float(tol), PREC[prec], flags, wp, wbytes, kp, _stream())
+        _check(st, "randutv_factor")
     return int(k.value) if (sync or tol > 0) else None
 
 

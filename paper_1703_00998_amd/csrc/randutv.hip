@@ -36,8 +36,14 @@ constexpr int kJacobiSweeps = 40;
 struct Layout {
   size_t Y, Vh, Vh2, Z, Uh, Uh2, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwU, TwU2, tauV, tauU, Rst,
       Ust, Vst, D, Jw, Jv, Ftmp, split, nrm, ints, panel, hr, total;
+  // Over-sampling (p > 0) only: QR and SVD of the extended sample.
+  size_t VY, TwY, RY, UR, VR, JwR, JvR, tauY, DR, Cy, Cy2, intsY;
   size_t split_elems;
 };
+
+// Ints per step for the SVD of the extended sample: the size word, the
+// status word and one rotation counter per sweep.
+constexpr int kIntsY = 2 + kJacobiSweeps;
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -45,9 +51,11 @@ int64_t num_steps(int64_t m, int64_t n, int64_t b) {
   return std::min((m + b - 1) / b, (n + b - 1) / b);
 }
 
-Layout make_layout(int64_t m, int64_t n, int64_t b) {
+// Sampling buffers Y and Z are b + p columns wide.
+Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   Layout L{};
   const int64_t s = num_steps(m, n, b);
+  const int64_t bp = b + p;
   const size_t d = sizeof(double);
   const size_t mb = (size_t)m * b, nb = (size_t)n * b, bb = (size_t)b * b;
   size_t off = 0;
@@ -56,10 +64,10 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
     off = al256(off + bytes);
     return o;
   };
-  L.Y = take(nb * d);
+  L.Y = take((size_t)n * bp * d);
   L.Vh = take(nb * d);
   L.Vh2 = take(nb * d);
-  L.Z = take(mb * d);
+  L.Z = take((size_t)m * bp * d);
   L.Uh = take(mb * d);
   L.Uh2 = take(mb * d);
   L.W = take(mb * d);
@@ -81,12 +89,27 @@ Layout make_layout(int64_t m, int64_t n, int64_t b) {
   L.Jw = take(s * bb * d);
   L.Jv = take(s * bb * d);
   L.Ftmp = take(std::max(mb, nb) * d);
-  L.split_elems = (size_t)kMaxSplitK * std::max(mb, nb);
+  L.split_elems = (size_t)kMaxSplitK * std::max(m, n) * bp;
   L.split = take(L.split_elems * d);
   L.nrm = take(1040 * d);
   L.ints = take((2 * s + s * kJacobiSweeps + 8) * sizeof(int));
-  L.panel = take(panel_work_bytes((int)b));
-  L.hr = take(hr_work_bytes(std::max(m, n), (int)b));
+  L.panel = take(panel_work_bytes((int)bp));
+  L.hr = take(hr_work_bytes(std::max(m, n), (int)bp));
+  if (p > 0) {
+    const size_t bpb = (size_t)bp * bp;
+    L.VY = take((size_t)n * bp * d);
+    L.TwY = take(bpb * d);
+    L.RY = take(bpb * d);
+    L.UR = take(bpb * d);
+    L.VR = take(bpb * d);
+    L.JwR = take(bpb * d);
+    L.JvR = take(bpb * d);
+    L.tauY = take(bp * d);
+    L.DR = take(bp * d);
+    L.Cy = take((size_t)bp * b * d);
+    L.Cy2 = take((size_t)bp * b * d);
+    L.intsY = take((size_t)s * kIntsY * sizeof(int));
+  }
   L.total = off;
   return L;
 }
@@ -169,6 +192,50 @@ __global__ void k_zero_int(int* p) {
   if (threadIdx.x == 0) p[0] = 0;
 }
 
+// Over-sampling (Remark on over-sampling, Section 5.3; Appendix A.2, Figure
+// of the over-sampled step): replace the Ni x (b+p) sample Y by its b
+// dominant left singular vectors, in the first b columns of Y.  With
+// Ni >= b+p: Y = Q_Y R_Y (Householder), R_Y = U_R S W^T, and the vectors
+// are Q_Y U_R(:, 0:b) = U1 - V_Y Tw_Y V_Y^T U1 with U1 = [U_R(:, 0:b); 0].
+// With Ni < b+p the SVD is taken of Y padded with zero rows to b+p, whose
+// leading Ni rows of the left singular vectors are those of Y.  Either way
+// the right singular vectors are Y's own, so the batched SVD's sign rule
+// (largest entry of each right vector positive) fixes each vector's sign.
+// `iy` holds the size word, the status word and the sweep counters.
+hipError_t oversample_basis(hipStream_t st, int Ni, int B, int Bp, double* Y, int64_t ldy,
+                            const Layout& L, char* base, int* iy, const HrWork& hw,
+                            const PanelWork& pw, double* split, size_t se) {
+  auto dp = [&](size_t off) { return (double*)(base + off); };
+  double *VY = dp(L.VY), *TwY = dp(L.TwY), *RY = dp(L.RY), *UR = dp(L.UR), *VR = dp(L.VR),
+         *JwR = dp(L.JwR), *JvR = dp(L.JvR), *tauY = dp(L.tauY), *DR = dp(L.DR), *Cy = dp(L.Cy),
+         *Cy2 = dp(L.Cy2);
+  const int64_t bb = (int64_t)Bp * Bp;
+  hipError_t e;
+  const bool tall = Ni >= Bp;
+  if (tall) {
+    e = panel_qr_hr(st, Ni, Bp, Y, ldy, VY, ldy, RY, Bp, tauY, TwY, Bp, hw, pw, split, se);
+  } else {
+    e = set_zero(st, Bp, Bp, RY, Bp);
+    if (e == hipSuccess) e = copy_matrix(st, Ni, Bp, Y, ldy, RY, Bp);
+  }
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(64), 0, st, iy, 1, Bp, Bp);
+  e = hipGetLastError();
+  if (e == hipSuccess)
+    e = batched_svd(st, 1, iy, Bp, RY, bb, UR, VR, bb, DR, Bp, JwR, JvR, iy + 1, kJacobiSweeps);
+  if (e != hipSuccess) return e;
+  if (!tall) return copy_matrix(st, Ni, B, UR, Bp, Y, ldy);
+  e = set_zero(st, Ni, B, Y, ldy);
+  if (e == hipSuccess) e = copy_matrix(st, Bp, B, UR, Bp, Y, ldy);
+  if (e == hipSuccess)  // Cy = V_Y(0:Bp, :)^T U1
+    e = gemm(st, PREC_FP64, true, false, Bp, B, Bp, 1.0, VY, ldy, UR, Bp, 0.0, Cy, Bp, nullptr, 0);
+  if (e == hipSuccess)
+    e = gemm(st, PREC_FP64, false, false, Bp, B, Bp, 1.0, TwY, Bp, Cy, Bp, 0.0, Cy2, Bp, nullptr, 0);
+  if (e == hipSuccess)
+    e = gemm(st, PREC_FP64, false, false, Ni, B, Bp, -1.0, VY, ldy, Cy2, Bp, 1.0, Y, ldy, split, se);
+  return e;
+}
+
 #define HIPCHK(x)                                   \
   do {                                              \
     hipError_t e_ = (x);                            \
@@ -176,6 +243,14 @@ __global__ void k_zero_int(int* p) {
   } while (0)
 
 }  // namespace
+
+namespace rutv {
+// factor_impl with over-sampling p (b + p samples per randomized step).
+int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,
+                const double* G, int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv,
+                int64_t k_stop, double tol, int prec, unsigned flags, void* work,
+                size_t work_bytes, int64_t* k_out, void* stream, const ApproxTape* tape);
+}  // namespace rutv
 
 extern "C" {
 
@@ -188,9 +263,24 @@ int64_t randutv_random_steps(int64_t m, int64_t n, int64_t b) {
   return c;
 }
 
-int64_t randutv_g_cols(int64_t m, int64_t n, int64_t b) {
+int64_t randutv_g_cols_p(int64_t m, int64_t n, int64_t b, int64_t p) {
   const int64_t r = randutv_random_steps(m, n, b);
-  return r < 0 ? -1 : r * b;
+  return (r < 0 || p < 0) ? -1 : r * (b + p);
+}
+
+int64_t randutv_g_cols(int64_t m, int64_t n, int64_t b) { return randutv_g_cols_p(m, n, b, 0); }
+
+int randutv_workspace_size_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, int prec,
+                             unsigned flags, size_t* bytes) {
+  if (n < 1 || m < 1) return -1;
+  if (b < 1 || b > kMaxB) return -3;
+  if (p < 0 || b + p > kMaxB) return -4;
+  if (q < 0 || q > 16) return -5;
+  if (prec < 0 || prec > 3) return -6;
+  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -7;
+  if (!bytes) return -8;
+  *bytes = make_layout(m, n, b, p).total;
+  return 0;
 }
 
 int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, unsigned flags,
@@ -223,6 +313,14 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
   return rutv::factor_impl(m, n, b, q, T, ldt, G, ldg, U, ldu, V, ldv, k_stop, tol, prec, flags,
                            work, work_bytes, k_out, stream, nullptr);
 }
+
+int randutv_factor_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,
+                     const double* G, int64_t ldg, double* U, int64_t ldu, double* V,
+                     int64_t ldv, int64_t k_stop, double tol, int prec, unsigned flags,
+                     void* work, size_t work_bytes, int64_t* k_out, void* stream) {
+  return rutv::factor_core(m, n, b, p, q, T, ldt, G, ldg, U, ldu, V, ldv, k_stop, tol, prec, flags,
+                     work, work_bytes, k_out, stream, nullptr);
+}
 }  // extern "C"
 
 namespace rutv {
@@ -233,13 +331,23 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
                 int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv, int64_t k_stop,
                 double tol, int prec, unsigned flags, void* work, size_t work_bytes,
                 int64_t* k_out, void* stream, const ApproxTape* tape) {
+  return factor_core(m, n, b, 0, q, T, ldt, G, ldg, U, ldu, V, ldv, k_stop, tol, prec, flags, work,
+                     work_bytes, k_out, stream, tape);
+}
+
+int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,
+                const double* G, int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv,
+                int64_t k_stop, double tol, int prec, unsigned flags, void* work,
+                size_t work_bytes, int64_t* k_out, void* stream, const ApproxTape* tape) {
   if (m < 1 || n < 1) return -1;
   if (m < n && tape) return RANDUTV_E_UNSUPPORTED;  // the approximation takes m >= n
+  if (p > 0 && tape) return RANDUTV_E_UNSUPPORTED;
   if (std::max(m, n) > kMaxPanelRows || m * n > ((int64_t)1 << 40)) return RANDUTV_E_UNSUPPORTED;
   if (b < 1 || b > kMaxB) return -2;
+  if (p < 0 || b + p > kMaxB) return -13;
   if (q < 0 || q > 16) return -3;
   if (!T || ldt < m) return -4;
-  const int64_t gcols = randutv_g_cols(m, n, b);
+  const int64_t gcols = randutv_g_cols_p(m, n, b, p);
   if (gcols > 0 && (!G || ldg < m)) return -5;
   const bool formU = flags & RANDUTV_FORM_U, formV = flags & RANDUTV_FORM_V;
   if (formU && (!U || ldu < m)) return -6;
@@ -247,7 +355,7 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
   if (prec < 0 || prec > 3) return -10;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -11;
   if (!work || ((uintptr_t)work & 255)) return -12;
-  const Layout L = make_layout(m, n, b);
+  const Layout L = make_layout(m, n, b, p);
   if (work_bytes < L.total) return RANDUTV_E_WORKSPACE;
 
   hipStream_t st = (hipStream_t)stream;
@@ -264,15 +372,18 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
   int* nbs = ints;
   int* jstatus = ints + s;
   PanelWork pw;
-  panel_work_carve(base + L.panel, (int)b, &pw);
+  panel_work_carve(base + L.panel, (int)(b + p), &pw);
   HrWork hw;
-  hr_work_carve(base + L.hr, std::max(m, n), (int)b, &hw);
+  hr_work_carve(base + L.hr, std::max(m, n), (int)(b + p), &hw);
   // Arithmetic of the sampling products (ps) and of the trailing updates (pu).
   const Prec ps = prec == kPrecMixed ? PREC_BF16X3 : (Prec)prec;
   const Prec pu = prec == kPrecMixed ? PREC_FP32 : (Prec)prec;
   const size_t se = L.split_elems;
   const int M = (int)m, N = (int)n, B = (int)b;
+  const int Bp = (int)(b + p);    // samples per randomized step
   const int MN = std::max(M, N);  // leading dimension of the U / V stream products
+  int* intsY = p > 0 ? (int*)(base + L.intsY) : nullptr;
+  int nrand = 0;  // randomized steps taken
 
   double* const VhS[2] = {dp(L.Vh), dp(L.Vh2)};
   double* const UhS[2] = {dp(L.Uh), dp(L.Uh2)};
@@ -331,13 +442,16 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
       RU = tape->Ru(i);
     }
     if (r0 + B < M && r0 + B < N) {
-      const double* Gi = G + (int64_t)i * b * ldg;
-      // Sampling matrix Y = (X^T X)^q X^T G_i.
-      HIPCHK(gemm(st, ps, true, false, Ni, B, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se));
+      const double* Gi = G + (int64_t)i * Bp * ldg;
+      // Sampling matrix Y = (X^T X)^q X^T G_i (b + p columns).
+      HIPCHK(gemm(st, ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se));
       for (int it = 0; it < q; ++it) {
-        HIPCHK(gemm(st, ps, false, false, Mi, B, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se));
-        HIPCHK(gemm(st, ps, true, false, Ni, B, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
+        HIPCHK(gemm(st, ps, false, false, Mi, Bp, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se));
+        HIPCHK(gemm(st, ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
       }
+      if (p > 0) HIPCHK(oversample_basis(st, Ni, B, Bp, Y, N, L, base, intsY + (size_t)i * kIntsY,
+                                         hw, pw, split, se));
+      ++nrand;
       // [Vq, ~] = qr(Y)
       HIPCHK(reclaim(4 + sl, vpend[sl]));
       HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, RV, B, tauV, TwV, B, hw, pw, split, se));
@@ -495,6 +609,12 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
     HIPCHK(hipMemcpy(js.data(), jstatus, nsvd * sizeof(int), hipMemcpyDeviceToHost));
     for (int v : js)
       if (v < 0) return 1;
+    if (p > 0 && nrand > 0) {  // the SVDs of the extended samples
+      std::vector<int> ys((size_t)nrand * kIntsY);
+      HIPCHK(hipMemcpy(ys.data(), intsY, ys.size() * sizeof(int), hipMemcpyDeviceToHost));
+      for (int i = 0; i < nrand; ++i)
+        if (ys[(size_t)i * kIntsY + 1] < 0) return 1;
+    }
   }
   return 0;
 }

@@ -53,6 +53,10 @@ def test_step_counts(lib):
     assert lib.randutv_random_steps(50, 40, 64) == 0
     assert lib.randutv_random_steps(20000, 5000, 128) == 39
     assert lib.randutv_random_steps(0, 5, 2) == -1
+    # Over-sampling: b + p columns per randomized step.
+    assert lib.randutv_g_cols_p(500, 500, 32, 0) == 480
+    assert lib.randutv_g_cols_p(500, 500, 32, 5) == 15 * 37
+    assert lib.randutv_g_cols_p(500, 500, 32, -1) == -1
 
 
 def test_workspace_and_argument_validation(lib):
@@ -93,6 +97,31 @@ def test_workspace_and_argument_validation(lib):
     assert call(work=vp(4096 + 8)) == -12   # misaligned
     assert call(work=vp(4096), wb=16) == -901
     assert lib.randutv_strerror(-900) == b"unsupported case"
+
+
+def test_oversampled_entry_points_validate(lib):
+    sz = ctypes.c_size_t(0)
+    sz0 = ctypes.c_size_t(0)
+    assert lib.randutv_workspace_size_p(100, 80, 16, 0, 1, 0, 3, ctypes.byref(sz)) == 0
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 3, ctypes.byref(sz0)) == 0
+    assert sz.value == sz0.value           # p = 0 is the plain layout
+    assert lib.randutv_workspace_size_p(100, 80, 16, 8, 1, 0, 3, ctypes.byref(sz)) == 0
+    assert sz.value > sz0.value
+    assert lib.randutv_workspace_size_p(100, 80, 16, -1, 1, 0, 3, ctypes.byref(sz)) == -4
+    assert lib.randutv_workspace_size_p(100, 80, 250, 7, 1, 0, 3, ctypes.byref(sz)) == -4
+    assert lib.randutv_workspace_size_p(100, 80, 16, 4, -1, 0, 3, ctypes.byref(sz)) == -5
+    vp = ctypes.c_void_p
+    null = vp(0)
+    fake = vp(1 << 20)  # never dereferenced: validation fails first
+
+    def call(p=4, b=16, G=fake, ldg=100, work=null, wb=0):
+        return lib.randutv_factor_p(100, 80, b, p, 1, fake, 100, G, ldg, null, 100, null, 80,
+                                    0, 0.0, 0, 0, work, wb, None, null)
+    assert call(p=-1) == -13
+    assert call(b=250, p=7) == -13
+    assert call(G=null) == -5
+    assert call() == -12
+    assert call(work=vp(4096), wb=16) == -901
 
 
 def test_gemm_and_panel_validation(lib):
