@@ -269,6 +269,138 @@ def oversample_run(B, torch, wl):
         return {"error": repr(e)}
 
 
+def study_ks(n, b):
+    """Ranks at which the spectral error is evaluated: every b/2 up to n/4,
+    every b after, and every k around the gap of Matrix 3 (k = 140..160)."""
+    h = max(1, b // 2)
+    ks = set(range(h, n // 4 + 1, h)) | set(range(n // 4, n, b)) | set(range(140, 161))
+    return sorted(k for k in ks if 0 < k < n)
+
+
+def spectral_norm(torch, M, direct_max=256, max_steps=160, seed=0):
+    """||M||_2.  Blocks of order <= direct_max: from the library SVD.  Larger
+    ones: Golub-Kahan-Lanczos bidiagonalization with full
+    reorthogonalization (twice per vector), stopped when the largest singular
+    value of the bidiagonal, taken every 10 steps, has not changed by 1e-13
+    relatively since the last one
+    (Kaniel-Paige: for the study's spectra 100-160 steps reach that); a
+    dense SVD of a 4000 x 4000 block per rank would dominate the study."""
+    import numpy as np
+    m, n = M.shape
+    if min(m, n) <= direct_max:
+        return torch.linalg.matrix_norm(M, ord=2).item()
+    steps = min(max_steps, min(m, n))
+    g = torch.Generator(device=M.device).manual_seed(seed)
+    Um = torch.zeros((m, steps), dtype=M.dtype, device=M.device)
+    Vm = torch.zeros((n, steps), dtype=M.dtype, device=M.device)
+    v = torch.randn(n, dtype=M.dtype, device=M.device, generator=g)
+    Vm[:, 0] = v / torch.linalg.norm(v)
+    alpha, beta = [], []  # diagonal and superdiagonal of the bidiagonal
+
+    def estimate():
+        return float(np.linalg.norm(np.diag(alpha) + np.diag(beta[:len(alpha) - 1], 1), 2))
+
+    last = []  # estimates every 10 steps
+    for j in range(steps):
+        u = M @ Vm[:, j]
+        if j > 0:
+            u = u - beta[-1] * Um[:, j - 1]
+            for _ in range(2):
+                u = u - Um[:, :j] @ (Um[:, :j].T @ u)
+        a = torch.linalg.norm(u).item()
+        if a == 0.0:  # the Krylov space is exhausted
+            break
+        alpha.append(a)
+        Um[:, j] = u / a
+        w = M.T @ Um[:, j] - a * Vm[:, j]
+        for _ in range(2):
+            w = w - Vm[:, :j + 1] @ (Vm[:, :j + 1].T @ w)
+        bnext = torch.linalg.norm(w).item()
+        if (j + 1) % 10 == 0:
+            last.append(estimate())
+            if len(last) > 1 and abs(last[-1] - last[-2]) <= 1e-13 * last[-1]:
+                break
+        if j + 1 == steps or bnext <= 1e-15 * max(alpha):
+            break
+        beta.append(bnext)
+        Vm[:, j + 1] = w / bnext
+    return estimate()
+
+
+def rank_k_errors(torch, T, sig, ks, norm2=None):
+    """Errors of the rank-k truncations A_k = U(:, 1:k) T(1:k, :) V^T
+    (Section 6.2, eqs. def_error, Ak_randUTV, rel_error) from T alone: since
+    T is upper triangular, A - A_k = U(:, k+1:) T(k+1:, k+1:) V(:, k+1:)^T,
+    so e_k = ||T(k+1:, k+1:)|| in any unitarily invariant norm.  Returns
+    numpy arrays: the Frobenius e_k for k = 0..n-1 (suffix sums of squares),
+    the spectral e_k for k in ks, and the optimal errors (sigma_{k+1} and
+    (sum_{j>k} sigma_j^2)^(1/2))."""
+    import numpy as np
+    n = min(T.shape)
+    Tn = T[:n, :n]
+    sq = Tn * Tn
+    # C[i, j] = sum_{i' >= i} T(i', j)^2; row k summed over j is ||T(k:, k:)||_F^2
+    # (the entries left of column k in rows >= k are zero).
+    col = torch.flip(torch.cumsum(torch.flip(sq, [0]), 0), [0])
+    fro = torch.sqrt(col.sum(1)).cpu().numpy()
+    if T.shape[0] > n:  # rows below n of a tall T: none in the study, kept for generality
+        fro = np.sqrt(fro ** 2 + np.array(
+            [torch.linalg.norm(T[n:, k:]).item() ** 2 for k in range(n)]))
+    norm2 = norm2 or spectral_norm
+    spec = np.array([norm2(torch, T[k:, k:]) for k in ks])
+    s = np.asarray(sig, dtype=np.float64)
+    opt_fro = np.sqrt(np.cumsum((s ** 2)[::-1])[::-1])  # opt_fro[k] = (sum_{j>=k} s_j^2)^(1/2)
+    return {"fro": fro, "spec": spec, "opt_spec": s[np.asarray(ks)], "opt_fro": opt_fro[:n]}
+
+
+def accuracy_study(B, torch, wl, n=4000, b=100, qs=(0, 1, 2)):
+    """The rank-k accuracy study of Section 6.2 on this library's factor:
+    Matrices 1-3 (fast decay, S-shaped, gap) of size n x n, block size b,
+    q = 0, 1, 2, FP64.  Per case: relative spectral and Frobenius errors
+    e_k / e_k^optimal over the rank grid (in %), |T_kk - sigma_k| / sigma_k,
+    and for Matrix 3 the diagonal at the gap (k = 150, 151)."""
+    import numpy as np
+    ks = study_ks(n, b)
+    out = {"config": f"{n}x{n}, b={b}, FP64, U and V not formed (e_k needs only T); "
+                     f"spectral e_k at {len(ks)} ranks, Frobenius e_k at every rank",
+           "ks": ks}
+    for name, fn in wl.STUDY_SPECTRA.items():
+        sig = fn(n)
+        A = wl.planted(n, n, sig, seed=0)
+        dA = B.colmajor(A)
+        del A
+        dG = B.colmajor(wl.gaussian_g(n, n, b, seed=1))
+        for q in qs:
+            T = dA.clone().T.contiguous().T
+            t0 = time.perf_counter()
+            B.randutv_factor(T, dG, b, q)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            t1 = time.perf_counter()
+            e = rank_k_errors(torch, T, sig, ks)
+            # The bidiagonalization against a dense SVD at two ranks.
+            chk = [k for k in (ks[0], 150) if k in ks]
+            dev = max(abs(e["spec"][ks.index(k)] / torch.linalg.matrix_norm(T[k:, k:], ord=2).item()
+                          - 1.0) for k in chk)
+            rs = 100.0 * e["spec"] / e["opt_spec"]
+            rf = 100.0 * e["fro"][1:] / e["opt_fro"][1:]
+            d = torch.diagonal(T).cpu().numpy()
+            dr = np.abs(d - sig) / sig
+            r = {"factor_ms": ms, "metrics_s": time.perf_counter() - t1,
+                 "rel_spec_pct_median": float(np.median(rs)), "rel_spec_pct_max": float(rs.max()),
+                 "rel_spec_pct_at": {int(k): float(v) for k, v in zip(ks, rs)
+                                     if k in (b, 2 * b, 5 * b, 10 * b, 150, n // 2)},
+                 "rel_fro_pct_median": float(np.median(rf)), "rel_fro_pct_max": float(rf.max()),
+                 "eckart_young_min_ratio": float(min(rs.min(), rf.min()) / 100.0),
+                 "diag_rel_err_median": float(np.median(dr)), "diag_rel_err_max": float(dr.max()),
+                 "spectral_check_rel_dev": float(dev)}
+            if name == "gap":
+                r["diag_rel_err_150_151"] = [float(dr[149]), float(dr[150])]
+            log(f"study {name} q={q}: {json.dumps(r)}")
+            out[f"{name}_q{q}"] = r
+    return out
+
+
 def approx_run(B, torch, wl):
     """2048 x 1024, sigma_j = exp(-j/100), b = 64, q = 1, k = 128: forward
     A_k and the hand-written backward of L = ||A_k - B||^2, FP64 storage,
@@ -313,6 +445,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the early-stop and differentiation workload timings")
     ap.add_argument("--cpu-n", type=int, default=1024)
+    ap.add_argument("--study", choices=["accuracy"],
+                    help="instead of the timing line, run the rank-k accuracy study of "
+                         "Section 6.2 (4000 x 4000, b = 100, q = 0, 1, 2) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -330,6 +465,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
     B.lib()
+    if args.study == "accuracy":
+        print(json.dumps({"study": "rank-k accuracy (Section 6.2)",
+                          **accuracy_study(B, torch, wl)}), flush=True)
+        return
     cfg = wl.CONFIGS["c3_8000"]
     m, n, b, q = cfg["m"], cfg["n"], cfg["b"], args.q
     t0 = time.perf_counter()

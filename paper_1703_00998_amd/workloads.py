@@ -14,7 +14,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["haar", "planted", "gaussian_g", "g_cols", "config_matrix",
-           "CONFIGS", "fast_decay_sigma", "gap_sigma"]
+           "CONFIGS", "fast_decay_sigma", "gap_sigma", "s_shape_sigma", "STUDY_SPECTRA"]
 
 
 def haar(rng, n, k):
@@ -63,6 +63,22 @@ def gap_sigma(n):
     """Matrix 3 of Section 6.2: 1/j for j <= 150, 0.1/j after."""
     j = np.arange(1, n + 1, dtype=np.float64)
     return np.where(j <= 150, 1.0 / j, 0.1 / j)
+
+
+def s_shape_sigma(n, floor=1e-2):
+    """Matrix 2 of Section 6.2 (S-shaped decay: near 1, a rapid drop, then
+    level at 1e-2; the paper gives only a plot).  Reading: log10 sigma_j
+    follows a logistic step from 0 to log10(floor), centred at j = n/8 with
+    width n/80, so sigma_1 ~ 1 and sigma_n ~ 1e-2."""
+    j = np.arange(1, n + 1, dtype=np.float64)
+    s = 1.0 / (1.0 + np.exp(-(j - n / 8.0) / (n / 80.0)))
+    return 10.0 ** (np.log10(floor) * s)
+
+
+# Spectra of the rank-k accuracy study (Section 6.2; Matrix 4, the boundary
+# integral operator, needs a discretization that is not part of this code).
+STUDY_SPECTRA = {"fast_decay": fast_decay_sigma, "s_shape": s_shape_sigma,
+                 "gap": gap_sigma}
 
 
 def _sigma_exp(n, scale):
