@@ -42,7 +42,7 @@ __all__ = [
     "householder", "house_qr", "apply_right", "apply_left", "small_svd",
     "top_left_singular_vectors",
     "num_steps", "num_random_steps", "g_slab", "randutv", "approx",
-    "approx_jvp", "flops_paper", "flops_uv",
+    "approx_jvp", "rsvd", "flops_paper", "flops_uv",
 ]
 
 
@@ -314,6 +314,43 @@ def approx_jvp(A, G, b, q, k, dA, h=1e-30):
     Ac = np.asarray(A, dtype=np.complex128) + 1j * h * np.asarray(dA, dtype=np.float64)
     Ak, _ = approx(Ac, np.asarray(G, dtype=np.float64), b, q, k)
     return np.imag(Ak) / h
+
+
+# --------------------------------------------------------------------------
+# Section 2.5, Remark RSVD (eqs. panda1, panda2) and Remark on over-sampling:
+# the two-stage randomized SVD on the same building blocks.
+# --------------------------------------------------------------------------
+def rsvd(A, k, q, G, p=0):
+    """Rank-k randomized SVD A ~ U diag(D) V^T.
+
+    Stage one, the range finder of Section 2.5: Y = (A^T A)^q A^T G with G
+    of size m x (k+p), Q = the orthonormal factor of Y's unpivoted
+    Householder QR (n x (k+p)).  Stage two, Remark RSVD: B = A Q, the
+    economic SVD B = Ub diag(Db) Vb^T (signs as in `small_svd`: the
+    largest-magnitude entry of each right singular vector positive), then
+    U = Ub, V = Q Vb.  With over-sampling (p > 0) the rank-(k+p) result is
+    truncated to its k dominant triplets.  Returns (U m x k, D (k,),
+    V n x k, Q n x (k+p)).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    c = k + p
+    if k < 1 or p < 0 or q < 0 or c > min(m, n):
+        raise ValueError("rsvd oracle: 1 <= k, 0 <= p, k + p <= min(m, n), q >= 0")
+    Y = A.T @ G[:, :c]
+    for _ in range(q):
+        Y = A.T @ (A @ Y)
+    refl, _ = house_qr(Y)
+    Q = apply_right(np.eye(n), refl)[:, :c]     # H_0 ... H_{c-1} [I; 0]
+    B = A @ Q
+    Ub, Db, Wt = np.linalg.svd(B, full_matrices=False)
+    W = Wt.T.copy()
+    for j in range(c):
+        idx = int(np.argmax(np.abs(W[:, j])))
+        if W[idx, j] < 0.0:
+            W[:, j] = -W[:, j]
+            Ub[:, j] = -Ub[:, j]
+    return Ub[:, :k].copy(), Db[:k].copy(), Q @ W[:, :k], Q
 
 
 # --------------------------------------------------------------------------

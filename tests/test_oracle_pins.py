@@ -498,3 +498,87 @@ def test_zero_matrix():
     U, T, V, k = ref.randutv(A, 4, 1, G)
     assert np.all(T == 0.0) and np.all(np.isfinite(U)) and np.all(np.isfinite(V))
     np.testing.assert_allclose(U.T @ U, np.eye(20), atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Randomized SVD (Section 2.5, Remark RSVD, eqs. panda1, panda2).
+# --------------------------------------------------------------------------
+def _rsvd_case(m=120, n=90, decay=8.0, seed=4):
+    sig = np.exp(-np.arange(1, min(m, n) + 1) / decay)
+    return wl.planted(m, n, sig, seed=seed), sig
+
+
+@pytest.mark.parametrize("k,p,q", [(10, 0, 0), (10, 0, 2), (12, 6, 1), (30, 10, 1)])
+def test_rsvd_matches_dense_lapack_version(k, p, q):
+    """The oracle's RSVD against a dense re-implementation on LAPACK
+    primitives (scipy's dgeqrf/dorgqr Q of the sample, whose reflectors use
+    the same dlarfg convention, and gesdd of B), with the same sign rule."""
+    A, _ = _rsvd_case()
+    G = np.random.default_rng(1).standard_normal((A.shape[0], k + p))
+    U, D, V, Q = ref.rsvd(A, k, q, G, p=p)
+    Y = A.T @ G
+    for _ in range(q):
+        Y = A.T @ (A @ Y)
+    Ql, _ = scipy.linalg.qr(Y, mode="economic")
+    # Householder QR is backward stable, so two orderings of its rounding give
+    # Q's that differ by about eps * cond(Y).
+    tol = max(1e-12, 1e-14 * np.linalg.cond(Y))
+    np.testing.assert_allclose(Q, Ql, rtol=0, atol=tol)
+    Ub, Db, Wt = scipy.linalg.svd(A @ Ql, full_matrices=False, lapack_driver="gesdd")
+    for j in range(k):
+        if Wt[j, np.argmax(np.abs(Wt[j]))] < 0:
+            Wt[j] *= -1
+            Ub[:, j] *= -1
+    np.testing.assert_allclose(D, Db[:k], rtol=1e-12)
+    np.testing.assert_allclose(U, Ub[:, :k], rtol=0, atol=max(1e-10, tol))
+    np.testing.assert_allclose(V, Ql @ Wt[:k].T, rtol=0, atol=max(1e-10, tol))
+
+
+def test_rsvd_error_equals_range_finder_error():
+    """Remark RSVD: stage two is exact, so A - U D V^T = A - A Q Q^T (p = 0)
+    in both norms; with p > 0, U D V^T is the best rank-k approximation of
+    A Q Q^T (Eckart-Young on B = A Q)."""
+    A, _ = _rsvd_case()
+    m, n = A.shape
+    k = 15
+    G = np.random.default_rng(1).standard_normal((m, k + 8))
+    U, D, V, Q = ref.rsvd(A, k, 1, G[:, :k])
+    E1 = A - (U * D) @ V.T
+    E2 = A - A @ Q @ Q.T
+    assert abs(np.linalg.norm(E1) - np.linalg.norm(E2)) <= 1e-13 * np.linalg.norm(A)
+    assert abs(np.linalg.norm(E1, 2) - np.linalg.norm(E2, 2)) <= 1e-13 * np.linalg.norm(A)
+    U, D, V, Q = ref.rsvd(A, k, 1, G, p=8)
+    P = A @ Q @ Q.T
+    Up, Dp, Vpt = np.linalg.svd(P)
+    best = (Up[:, :k] * Dp[:k]) @ Vpt[:k]
+    np.testing.assert_allclose((U * D) @ V.T, best, rtol=0, atol=1e-12 * np.linalg.norm(A))
+    # U, V orthonormal; D descending and nonnegative.
+    assert np.linalg.norm(U.T @ U - np.eye(k)) <= 1e-13 and np.linalg.norm(V.T @ V - np.eye(k)) <= 1e-13
+    assert np.all(np.diff(D) <= 0) and D[-1] >= 0
+
+
+def test_rsvd_exact_on_rank_le_k():
+    """rank(A) = 7 <= k = 10: the range finder captures the row space, so
+    U D V^T = A and D holds the singular values (then zeros)."""
+    sig = np.array([4.0, 3.0, 2.0, 1.0, 0.5, 0.25, 0.125])
+    A = wl.planted(80, 60, sig, seed=3)
+    G = np.random.default_rng(1).standard_normal((80, 10))
+    U, D, V, _ = ref.rsvd(A, 10, 0, G)
+    np.testing.assert_allclose(D[:7], sig, rtol=1e-13)
+    assert np.all(np.abs(D[7:]) <= 1e-13)
+    np.testing.assert_allclose((U * D) @ V.T, A, rtol=0, atol=1e-13 * 4)
+
+
+def test_rsvd_range_matches_randutv_first_step():
+    """Section 5.3 (connection between RSVD and randUTV): with k = b and the
+    same G_1, RSVD's Q spans randUTV's first block of V, so the RSVD error
+    equals ||T(:, b:)||_F after randUTV's first step, and D equals the first
+    diagonal block of T (sigma(A Q) in both)."""
+    m, n, b, q = 60, 50, 8, 1
+    A = wl.planted(m, n, np.exp(-np.arange(1, 51) / 6.0), seed=2)
+    G = wl.gaussian_g(m, n, b, seed=1)
+    _, T, _, k = ref.randutv(A, b, q, G, k_stop=b)
+    U, D, V, Q = ref.rsvd(A, b, q, G[:, :b])
+    e = np.linalg.norm(A - (U * D) @ V.T)
+    assert abs(e - np.linalg.norm(T[:, b:])) <= 1e-12 * e
+    np.testing.assert_allclose(D, np.diag(T)[:b], rtol=1e-12)
