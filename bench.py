@@ -269,6 +269,41 @@ def oversample_run(B, torch, wl):
         return {"error": repr(e)}
 
 
+def rsvd_run(B, torch, wl, dA=None, sig=None):
+    """Randomized SVD (Section 2.5, Remark RSVD) of the 8000 x 8000 workload,
+    q = 1, rank k = 256 (p = 0) and k = 240 with p = 0 and p = 16 (k + p is
+    at most 256): time per call (inputs resident) and ||A - U D V^T||_F over
+    the optimal rank-k error, FP64 and the headline split path."""
+    import numpy as np
+    try:
+        m = n = 8000
+        q = 1
+        if dA is None:
+            A, sig = wl.config_matrix("c3_8000")
+            dA = B.colmajor(A)
+            del A
+        nA = torch.linalg.norm(dA).item()
+        out = {"config": "8000x8000, sigma_j=exp(-j/800)+1e-10, q=1, G from default_rng(1)"}
+        for k, p in ((256, 0), (240, 0), (240, 16)):
+            opt = float(np.sqrt(np.sum(np.asarray(sig)[k:] ** 2)))
+            dG = B.colmajor(np.random.default_rng(1).standard_normal((m, k + p)))
+            for prec in ("fp64", "bf16x3_fp32"):
+                res = {}
+
+                def step():
+                    res["f"] = B.randutv_rsvd(dA, dG, k, q, p=p, prec=prec, sync=False)
+
+                ms = _timed(torch, step, 5)
+                U, D, V = res["f"]
+                err = torch.linalg.norm(dA - (U * D) @ V.T).item()
+                r = {"ms": ms, "err_over_optimal": err / opt, "rel_err": err / nA}
+                log(f"rsvd k={k} p={p} [{prec}]: {r}")
+                out[f"k{k}_p{p}_{prec}"] = r
+        return out
+    except Exception as e:  # reported, never fatal to the headline line
+        return {"error": repr(e)}
+
+
 def study_ks(n, b):
     """Ranks at which the spectral error is evaluated: every b/2 up to n/4,
     every b after, and every k around the gap of Matrix 3 (k = 140..160)."""
@@ -550,6 +585,7 @@ def main():
         out["approx_2048x1024"] = approx_run(B, torch, wl)
         out["wide_4000x8000"] = wide_run(B, torch, wl)
         out["oversample_4000"] = oversample_run(B, torch, wl)
+        out["rsvd_8000"] = rsvd_run(B, torch, wl, dA, sig)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_n}x{args.cpu_n} sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, b, q)

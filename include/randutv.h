@@ -163,6 +163,48 @@ int randutv_factor_p(int64_t m, int64_t n, int64_t b, int64_t p, int q,
                      void* work, size_t work_bytes,
                      int64_t* k_out, void* stream);
 
+/*
+ * Randomized SVD on the same kernels (Section 2.5: the range finder and the
+ * Remark RSVD, eqs. panda1 and panda2; over-sampling per the Remark on
+ * over-sampling): A ~ U diag(D) V^T of rank k.
+ *   Y = (A^T A)^q A^T G (G: m x (k+p)), Q = the n x (k+p) orthonormal factor
+ *   of Y's unpivoted Householder QR, B = A Q, B = Ub diag(Db) W^T (economic
+ *   SVD), U = Ub(:, 0:k), D = Db(0:k), V = Q W(:, 0:k).  Each (u_j, v_j)
+ *   has the sign that makes the largest-magnitude entry of w_j positive.
+ *   With p = 0 the error A - U D V^T equals A - A Q Q^T exactly (in exact
+ *   arithmetic); with p > 0 the rank-(k+p) result is truncated to rank k.
+ *
+ *  1  m, n     rows and columns of A, max(m, n) <= 32768.
+ *  3  k        rank, k >= 1.
+ *  4  p        over-sampling, p >= 0, k + p <= min(m, n) and k + p <= 256.
+ *  5  q        power-iteration count, 0 <= q <= 16.
+ *  6  A, lda   m x n input (device, read only), lda >= m.
+ *  8  G, ldg   m x (k+p) N(0,1) matrix (device), ldg >= m.
+ * 10  U, ldu   out: m x k, orthonormal columns, ldu >= m.
+ * 12  D        out: k singular values, descending, >= 0.
+ * 13  V, ldv   out: n x k, orthonormal columns, ldv >= n.
+ * 15  prec     randutv_prec: the sampling products and B = A Q take the
+ *              arithmetic randutv_factor gives its sampling and update
+ *              products; the QRs, the SVD and U, V are FP64.
+ * 16  work     randutv_rsvd_workspace_size() bytes of device memory,
+ *              256-byte aligned; contents on entry are ignored.
+ * 18  sweeps_out  host pointer, may be NULL.  When non-NULL the call waits
+ *              for the stream, stores the Jacobi sweeps used and returns 1
+ *              if the SVD did not converge (RANDUTV_E_SYNC if a
+ *              cross-workgroup wait hit its spin limit); when NULL it only
+ *              enqueues.
+ * 19  stream
+ * Statuses: -i for argument i; RANDUTV_E_UNSUPPORTED above the size limit;
+ * RANDUTV_E_WORKSPACE; RANDUTV_E_HIP - hipError.
+ */
+int randutv_rsvd_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q,
+                                int prec, size_t* bytes);
+int randutv_rsvd(int64_t m, int64_t n, int64_t k, int64_t p, int q,
+                 const double* A, int64_t lda, const double* G, int64_t ldg,
+                 double* U, int64_t ldu, double* D, double* V, int64_t ldv,
+                 int prec, void* work, size_t work_bytes, int* sweeps_out,
+                 void* stream);
+
 /* ---- Building blocks of one step (exported for testing and reuse) ---- */
 
 /* Truncated approximation (Section 6.2, eq. Ak_randUTV; Theorem of Section

@@ -57,6 +57,11 @@ def lib():
     L.randutv_factor_p.argtypes = [i64, i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, i64,
                                    i64, dbl, i32, u32, vp, sz, ctypes.POINTER(i64), vp]
     L.randutv_factor_p.restype = i32
+    L.randutv_rsvd_workspace_size.argtypes = [i64, i64, i64, i64, i32, i32, ctypes.POINTER(sz)]
+    L.randutv_rsvd_workspace_size.restype = i32
+    L.randutv_rsvd.argtypes = [i64, i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, vp, i64,
+                               i32, vp, sz, ctypes.POINTER(i32), vp]
+    L.randutv_rsvd.restype = i32
     L.randutv_gemm.argtypes = [i32, i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl,
                                vp, i64, vp, sz, vp]
     L.randutv_gemm.restype = i32
@@ -96,7 +101,8 @@ def lib():
 
 EXPORTS = ["randutv_random_steps", "randutv_g_cols", "randutv_workspace_size",
            "randutv_factor", "randutv_g_cols_p", "randutv_workspace_size_p", "randutv_factor_p",
-           "randutv_gemm", "randutv_panel_work_size", "randutv_panel_qr",
+           "randutv_rsvd_workspace_size", "randutv_rsvd", "randutv_gemm",
+           "randutv_panel_work_size", "randutv_panel_qr",
            "randutv_small_svd_work_size", "randutv_small_svd", "randutv_strerror",
            "randutv_profile_begin", "randutv_profile_end", "randutv_profile_class_name",
            "randutv_approx_tape_size", "randutv_approx_work_size", "randutv_approx",
@@ -228,6 +234,30 @@ def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", w
             float(tol), PREC[prec], flags, wp, wbytes, kp, _stream())
         _check(st, "randutv_factor")
     return int(k.value) if (sync or tol > 0) else None
+
+
+def randutv_rsvd(A, G, k, q, p=0, prec="fp64", work=None, sync=True):
+    """Rank-k randomized SVD of A (m x n column-major FP64) with the m x (k+p)
+    Gaussian G: returns (U m x k, D (k,), V n x k).  sync=True waits and
+    checks the SVD's convergence."""
+    m, n = A.shape
+    out = ctypes.c_size_t(0)
+    _check(lib().randutv_rsvd_workspace_size(m, n, k, p, q, PREC[prec], ctypes.byref(out)),
+           "randutv_rsvd_workspace_size")
+    if work is None:
+        work = workspace(int(out.value), A.device)
+    wp, wbytes = _aligned_ptr(work)
+    if G.shape[1] < k + p:
+        raise RandUTVError(f"G needs {k + p} columns")
+    U = empty_colmajor(m, k, A.device)
+    V = empty_colmajor(n, k, A.device)
+    D = torch.empty(k, dtype=torch.float64, device=A.device)
+    sw = ctypes.c_int32(0)
+    _check(lib().randutv_rsvd(m, n, k, p, q, _ptr(A), _ld(A, m), _ptr(G), _ld(G, m), _ptr(U),
+                              _ld(U, m), _ptr(D), _ptr(V), _ld(V, n), PREC[prec], wp, wbytes,
+                              ctypes.byref(sw) if sync else None, _stream()),
+           "randutv_rsvd")
+    return U, D, V
 
 
 def randutv_gemm(C, A, B, ta=False, tb=False, alpha=1.0, beta=0.0, prec="fp64", work=None):

@@ -138,3 +138,31 @@ def test_gemm_and_panel_validation(lib):
     assert lib.randutv_panel_work_size(100, 0) == 0
     assert lib.randutv_panel_work_size(10, 20) == 0
     assert lib.randutv_panel_work_size(8000, 256) > 8000 * 256 * 8
+
+
+def test_rsvd_entry_points_validate(lib):
+    sz = ctypes.c_size_t(0)
+    assert lib.randutv_rsvd_workspace_size(300, 200, 20, 5, 1, 0, ctypes.byref(sz)) == 0
+    assert sz.value > 0
+    assert lib.randutv_rsvd_workspace_size(300, 200, 0, 5, 1, 0, ctypes.byref(sz)) == -3
+    assert lib.randutv_rsvd_workspace_size(300, 200, 20, -1, 1, 0, ctypes.byref(sz)) == -4
+    assert lib.randutv_rsvd_workspace_size(300, 200, 190, 20, 1, 0, ctypes.byref(sz)) == -4
+    assert lib.randutv_rsvd_workspace_size(300, 200, 250, 10, 1, 0, ctypes.byref(sz)) == -4
+    assert lib.randutv_rsvd_workspace_size(300, 200, 20, 5, 17, 0, ctypes.byref(sz)) == -5
+    assert lib.randutv_rsvd_workspace_size(300, 200, 20, 5, 1, 9, ctypes.byref(sz)) == -15
+    vp = ctypes.c_void_p
+    null = vp(0)
+    fake = vp(1 << 20)  # never dereferenced: validation fails first
+
+    def call(A=fake, lda=300, G=fake, ldg=300, U=fake, ldu=300, D=fake, V=fake, ldv=200,
+             work=null, wb=0):
+        return lib.randutv_rsvd(300, 200, 20, 5, 1, A, lda, G, ldg, U, ldu, D, V, ldv, 0,
+                                work, wb, None, null)
+    assert call(A=null) == -6
+    assert call(lda=299) == -6
+    assert call(G=null) == -8
+    assert call(U=null) == -10
+    assert call(D=null) == -12
+    assert call(ldv=199) == -13
+    assert call() == -16
+    assert call(work=vp(4096), wb=16) == -901

@@ -1,0 +1,113 @@
+"""GPU parity of the randomized SVD (randutv_rsvd; Section 2.5, Remark RSVD,
+eqs. panda1 and panda2, with the Remark on over-sampling) against the FP64
+oracle through the C ABI: U, D, V elementwise on shapes spanning several
+tiles with ragged tails, tall and wide, k + p above one 128-column panel
+block and at the 256 limit; the split-precision paths by their error; and
+at 4000 x 4000 the properties that hold at any size (orthonormal factors,
+singular values bounded by A's, Eckart-Young, and the error of k = b,
+p = 0 equal to randUTV's after its first step with the same G, Section 5.3).
+
+Tolerance: as for the over-sampled factorization, 100 times the oracle's
+own response to a seeded 1e-15 relative perturbation of A (individual
+singular vectors of B move with the gaps between its singular values), with
+1e-9 (U, V) and 1e-10 ||A||_2 (D) as the floor."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import randutv_ref as ref  # noqa: E402
+from paper_1703_00998_amd import workloads as wl  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_00998_amd import binding
+    binding.lib()
+    return binding
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _case(m, n, k, p, decay):
+    sig = np.exp(-np.arange(1, min(m, n) + 1) / decay)
+    A = wl.planted(m, n, sig, seed=0)
+    G = np.asfortranarray(np.random.default_rng(1).standard_normal((m, k + p)))
+    return A, G, sig
+
+
+CASES = [(300, 200, 20, 0, 1), (500, 400, 32, 8, 1), (257, 300, 40, 10, 2),
+         (1000, 700, 128, 0, 0), (600, 600, 120, 20, 1), (800, 600, 200, 56, 1)]
+
+
+@pytest.mark.parametrize("m,n,k,p,q", CASES)
+def test_rsvd_matches_oracle(B, m, n, k, p, q):
+    print(f"rsvd m={m} n={n} k={k} p={p} q={q}", flush=True)
+    A, G, _ = _case(m, n, k, p, decay=max(2.0 * k, 8.0))
+    Uo, Do, Vo, _ = ref.rsvd(A, k, q, G, p=p)
+    E = np.random.default_rng(12345).standard_normal(A.shape)
+    E *= 1e-15 * np.linalg.norm(A) / np.linalg.norm(E)
+    Up, Dp, Vp, _ = ref.rsvd(A + E, k, q, G, p=p)
+    tu = max(1e-9, 100 * np.abs(Uo - Up).max())
+    tv = max(1e-9, 100 * np.abs(Vo - Vp).max())
+    td = max(1e-10, 100 * np.abs(Do - Dp).max())
+    U, D, V = B.randutv_rsvd(B.colmajor(A), B.colmajor(G), k, q, p=p)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(_np(D), Do, rtol=0, atol=td)
+    np.testing.assert_allclose(_np(U), Uo, rtol=0, atol=tu)
+    np.testing.assert_allclose(_np(V), Vo, rtol=0, atol=tv)
+    assert np.all(np.diff(_np(D)) <= 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3_fp32"])
+def test_rsvd_split_paths(B, prec):
+    """1024 x 768, k = 64, p = 10, q = 1: the error of the split path within
+    1e-6 relative of the FP64 path's, U and V orthonormal to FP64 rounding."""
+    m, n, k, p, q = 1024, 768, 64, 10, 1
+    A, G, _ = _case(m, n, k, p, decay=100.0)
+    dA = B.colmajor(A)
+    dG = B.colmajor(G)
+    U, D, V = B.randutv_rsvd(dA, dG, k, q, p=p, prec=prec)
+    U64, D64, V64 = B.randutv_rsvd(dA, dG, k, q, p=p)
+    nA = torch.linalg.norm(dA).item()
+    e = torch.linalg.norm(dA - (U * D) @ V.T).item() / nA
+    e64 = torch.linalg.norm(dA - (U64 * D64) @ V64.T).item() / nA
+    assert abs(e - e64) <= 1e-6
+    eye = torch.eye(k, dtype=torch.float64, device="cuda")
+    assert torch.linalg.norm(U.T @ U - eye).item() <= 1e-12 * math.sqrt(m)
+    assert torch.linalg.norm(V.T @ V - eye).item() <= 1e-12 * math.sqrt(n)
+    assert np.abs(_np(D) - _np(D64)).max() <= 1e-5 * _np(D64)[0]
+
+
+def test_rsvd_full_size_properties(B):
+    """4000 x 4000 (sigma_j = j^-1.5), k = b = 128, q = 1, p = 0."""
+    m = n = 4000
+    k, q = 128, 1
+    sig = np.arange(1, n + 1, dtype=np.float64) ** -1.5
+    A = wl.planted(m, n, sig, seed=0)
+    G = wl.gaussian_g(m, n, k, seed=1)
+    dA = B.colmajor(A)
+    dG = B.colmajor(G)
+    U, D, V = B.randutv_rsvd(dA, dG, k, q)
+    eye = torch.eye(k, dtype=torch.float64, device="cuda")
+    assert torch.linalg.norm(U.T @ U - eye).item() <= 1e-12 * math.sqrt(m)
+    assert torch.linalg.norm(V.T @ V - eye).item() <= 1e-12 * math.sqrt(n)
+    d = _np(D)
+    assert np.all(np.diff(d) <= 0) and np.all(d <= sig[:k] * (1 + 1e-12))
+    err = torch.linalg.norm(dA - (U * D) @ V.T).item()
+    assert err >= math.sqrt(np.sum(sig[k:] ** 2)) * (1 - 1e-12)
+    # Section 5.3: the same range after randUTV's first step (same G slab).
+    T = dA.clone().T.contiguous().T
+    kk = B.randutv_factor(T, dG, k, q, k_stop=k)
+    assert kk == k
+    e_utv = torch.linalg.norm(T[:, k:]).item()
+    assert abs(err - e_utv) <= 1e-10 * err
+    np.testing.assert_allclose(d, _np(torch.diagonal(T))[:k], rtol=1e-10)
