@@ -556,17 +556,21 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     }
   }
 
-  if (sc) {  // join the U / V stream
-    HIPCHK(hipEventRecord(sc->ev[8], ss));
-    HIPCHK(hipStreamWaitEvent(st, sc->ev[8], 0));
-  }
+  auto join_side = [&]() -> hipError_t {
+    if (!sc) return hipSuccess;
+    hipError_t e = hipEventRecord(sc->ev[8], ss);
+    return e == hipSuccess ? hipStreamWaitEvent(st, sc->ev[8], 0) : e;
+  };
   if (tape) {  // truncated approximation: no small SVDs (U_k U_k^T does not see them)
+    HIPCHK(join_side());
     if (k_out) *k_out = k_done;
     return 0;
   }
   // Batched SVDs of the stashed R blocks, then fold the rotations back:
   // T(I2,J2) = Ds, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) = T(I1,J2) Vs,
-  // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.
+  // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.  The SVDs and T's part run
+  // while the U / V stream finishes its last products; U and V's part
+  // waits for it.
   const int nsvd = (int)widths.size();
   hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(256), 0, st, nbs, nsvd, B, widths.back());
   HIPCHK(batched_svd(st, nsvd, nbs, B, Rst, (int64_t)B * B, Ust, Vst, (int64_t)B * B, Dd, B, Jw, Jv,
@@ -588,6 +592,12 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       HIPCHK(gemm(st, PREC_FP64, false, false, r0, w, w, 1.0, blk, ldt, Vs, B, 0.0, Ftmp, r0, nullptr, 0));
       HIPCHK(copy_matrix(st, r0, w, Ftmp, r0, blk, ldt));
     }
+  }
+  HIPCHK(join_side());
+  for (int i = 0; i < nsvd && (formU || formV); ++i) {
+    const int r0 = i * B, w = widths[i];
+    const double* Us = Ust + (size_t)i * B * B;
+    const double* Vs = Vst + (size_t)i * B * B;
     if (formU) {
       double* blk = U + (int64_t)r0 * ldu;
       HIPCHK(gemm(st, PREC_FP64, false, false, M, w, w, 1.0, blk, ldu, Us, B, 0.0, Ftmp, M, nullptr, 0));
