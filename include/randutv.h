@@ -287,8 +287,12 @@ int randutv_small_svd(int64_t count, const int* nbs, int64_t ld, const double* R
  * 16*Mp*nb; 0 for the small SVDs) and launch counts.  Any of ms, flops,
  * bytes, launches may be NULL.  Returns the number of classes filled, or a
  * negative status.  Not thread-safe; meant for one process-wide measurement
- * at a time. */
+ * at a time.  randutv_profile_begin_class(c) records events around launches
+ * of class c only (c < 0: all classes, as randutv_profile_begin), so that
+ * a timed run carries the events of the one kernel it measures; returns -1
+ * for c beyond the last class. */
 int randutv_profile_begin(void);
+int randutv_profile_begin_class(int cls);
 int randutv_profile_end(int max_classes, double* ms, double* flops, double* bytes,
                         int64_t* launches);
 const char* randutv_profile_class_name(int cls);

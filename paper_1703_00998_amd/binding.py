@@ -76,6 +76,8 @@ def lib():
     L.randutv_small_svd.restype = i32
     L.randutv_profile_begin.argtypes = []
     L.randutv_profile_begin.restype = i32
+    L.randutv_profile_begin_class.argtypes = [i32]
+    L.randutv_profile_begin_class.restype = i32
     L.randutv_profile_end.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                       ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     L.randutv_profile_end.restype = i32
@@ -104,13 +106,25 @@ EXPORTS = ["randutv_random_steps", "randutv_g_cols", "randutv_workspace_size",
            "randutv_rsvd_workspace_size", "randutv_rsvd", "randutv_gemm",
            "randutv_panel_work_size", "randutv_panel_qr",
            "randutv_small_svd_work_size", "randutv_small_svd", "randutv_strerror",
-           "randutv_profile_begin", "randutv_profile_end", "randutv_profile_class_name",
+           "randutv_profile_begin", "randutv_profile_begin_class", "randutv_profile_end", "randutv_profile_class_name",
            "randutv_approx_tape_size", "randutv_approx_work_size", "randutv_approx",
            "randutv_approx_backward_work_size", "randutv_approx_backward"]
 
 
-def profile_begin():
-    _check(lib().randutv_profile_begin(), "randutv_profile_begin")
+def profile_begin(only=None):
+    """Start per-kernel timing; `only` = a class name restricts the events to
+    that kernel class."""
+    if only is None:
+        _check(lib().randutv_profile_begin(), "randutv_profile_begin")
+        return
+    for c in range(64):
+        name = lib().randutv_profile_class_name(c).decode()
+        if not name:
+            break
+        if name == only:
+            _check(lib().randutv_profile_begin_class(c), "randutv_profile_begin_class")
+            return
+    raise RandUTVError(f"unknown kernel class {only}")
 
 
 def profile_end(max_classes=64):

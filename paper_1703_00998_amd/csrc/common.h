@@ -38,7 +38,9 @@ constexpr int kPrecMixed = 3;
 enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
                  PC_SPLITK = 24, PC_PANEL, PC_SVD, PC_GEMM_SMALL, PC_COUNT };
 bool prof_on();
-int prof_mark(hipStream_t st);  // start event; returns a slot or -1 when off
+// Start event of a launch of class `cls`; returns a slot, or -1 when off or
+// when timing is restricted to another class.
+int prof_mark(hipStream_t st, int cls);
 void prof_suppress(int delta);  // +1 / -1 around launches timed by an enclosing mark
 // flops and bytes: the launch's algorithmic work and HBM operand traffic.
 void prof_done(hipStream_t st, int slot, int cls, double flops, double bytes);

@@ -382,7 +382,7 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   if (M <= 0 || N <= 0) return hipSuccess;
   if (prec == PREC_FP64 && M <= kSmallMN && N <= kSmallMN && K <= kSmallK) {
     const dim3 grid((M + 15) / 16, (N + 15) / 16);
-    const int slot = prof_mark(st);
+    const int slot = prof_mark(st, PC_GEMM_SMALL);
     if (!ta && !tb) hipLaunchKernelGGL((k_gemm_small<false, false>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
     else if (ta && !tb) hipLaunchKernelGGL((k_gemm_small<true, false>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
     else if (!ta && tb) hipLaunchKernelGGL((k_gemm_small<false, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
@@ -430,22 +430,22 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     al = 1.0;
     be = 0.0;
   }
-  const int slot = prof_mark(st);
+  const int cls = 12 * shape + 4 * (int)prec +
+                  (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN));
+  const int slot = prof_mark(st, cls);
   if (prec == PREC_FP32)
     launch_p<PREC_FP32>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else if (prec == PREC_BF16X3)
     launch_p<PREC_BF16X3>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else
     launch_p<PREC_FP64>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
-  prof_done(st, slot, 12 * shape + 4 * (int)prec +
-                          (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN)),
-            2.0 * M * N * (double)K,
+  prof_done(st, slot, cls, 2.0 * M * N * (double)K,
             8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;
   const int64_t total = (int64_t)M * N;
   int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-  const int slot2 = prof_mark(st);
+  const int slot2 = prof_mark(st, PC_SPLITK);
   hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, st, M, N, splits, splitws,
                      zs, C, ldc, alpha, beta);
   prof_done(st, slot2, PC_SPLITK, (double)splits * M * N,

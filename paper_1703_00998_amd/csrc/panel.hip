@@ -973,7 +973,7 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
       PanelArgs2 a{Mp, nb, nwg, chunk, ldS, nwg > 1 ? 1 : 0, P, ldp, tau, Tw, ldtw, w.part,
                    w.bcast, w.bpart, w.red, w.bar, w.err, gate, w.gram, w.qtop};
       void* args[] = {&a};
-      const int slot = prof_mark(st);
+      const int slot = prof_mark(st, PC_PANEL);
       hipError_t e;
       if (gate) {
         // Gated (fallback) use: nearly always skipped, every workgroup
@@ -1004,7 +1004,7 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
   PanelArgs a{Mp, nb, nwg, chunk, P, ldp, tau, Tw, ldtw, w.part, w.bcast, w.bpart, w.red,
               w.bar, w.err, gate};
   void* args[] = {&a};
-  const int slot = prof_mark(st);
+  const int slot = prof_mark(st, PC_PANEL);
   hipError_t e = hipLaunchCooperativeKernel((const void*)k_panel, dim3(nwg), dim3(256), args, 0, st);
   prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb, 16.0 * Mp * (double)nb);
   return e;

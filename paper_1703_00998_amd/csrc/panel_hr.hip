@@ -994,7 +994,7 @@ hipError_t panel_qr_hr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, d
                        size_t split_elems) {
   if (nb <= 0) return hipSuccess;
   if (nb > 2 * kBlk || Mp < nb) return hipErrorInvalidValue;
-  const int slot = prof_mark(st);
+  const int slot = prof_mark(st, PC_PANEL);
   prof_suppress(1);
   hipError_t e = hr_panel(st, Mp, nb, P, ldp, V, ldv, Rout, ldr, tau, Tw, ldtw, hw, split,
                           split_elems);

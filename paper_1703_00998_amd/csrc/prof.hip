@@ -18,6 +18,7 @@ struct Rec {
 };
 
 bool g_on = false;
+int g_only = -1;     // >= 0: time launches of this class only
 int g_suppress = 0;  // > 0 inside a composite region timed as one class
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
@@ -54,8 +55,8 @@ bool prof_on() { return g_on; }
 
 void prof_suppress(int delta) { g_suppress += delta; }
 
-int prof_mark(hipStream_t st) {
-  if (!g_on || g_suppress > 0) return -1;
+int prof_mark(hipStream_t st, int cls) {
+  if (!g_on || g_suppress > 0 || (g_only >= 0 && cls != g_only)) return -1;
   hipEvent_t a = take_event(), b = take_event();
   if (!a || !b) return -1;
   if (hipEventRecord(a, st) != hipSuccess) return -1;
@@ -78,15 +79,19 @@ using namespace rutv;
 
 extern "C" {
 
-int randutv_profile_begin(void) {
+int randutv_profile_begin_class(int cls) {
+  if (cls >= PC_COUNT) return -1;
   for (auto& r : g_recs) {
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);
   }
   g_recs.clear();
+  g_only = cls < 0 ? -1 : cls;
   g_on = true;
   return 0;
 }
+
+int randutv_profile_begin(void) { return randutv_profile_begin_class(-1); }
 
 int randutv_profile_end(int max_classes, double* ms, double* flops, double* bytes,
                         int64_t* launches) {

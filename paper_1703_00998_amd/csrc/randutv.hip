@@ -148,24 +148,34 @@ SideCtx* side_ctx() {
   return &c;
 }
 
-// FP64 product for the U / V stream on 64 x 64 tiles with the reduction cut
-// into launches of at most `chunk` (beta = 1 after the first): each
-// workgroup then runs for tens of microseconds, so a panel kernel on the
-// main stream, which needs most of a CU's LDS, finds a free CU quickly
-// instead of waiting for long side-stream workgroups to drain.
+// FP64 product for the U / V stream on 64 x 64 tiles, cut into launches of
+// at most kSideCols output columns and a reduction of at most `chunk`
+// (beta = 1 after the first).  A panel kernel on the main stream needs most
+// of a CU's LDS, and while a side launch still has workgroups queued, every
+// CU that frees up is refilled from it; so the panel starts only when a
+// side launch ends.  Short launches (about 130 us for the rank-b updates at
+// n = 8000) bound that wait, at some cost in tail effects of the side
+// products (measured: 1024 columns, 129.4 ms per factorization against
+// 134.6 ms uncut; 512-1536 within 1 ms of that).
 constexpr int kSideChunk = 256;     // reduction chunk of the thin products W = X Vh
 constexpr int kSideChunkUpd = 256;  // and of the rank-b updates X -= W2 Vh^T
+constexpr int kSideCols = 1024;     // output columns per launch
 hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha,
                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                      double* C, int64_t ldc, int chunk) {
-  for (int k0 = 0; k0 < K || k0 == 0; k0 += chunk) {
-    const int kc = std::min(chunk, K - k0);
-    const double* Ak = A + (ta ? (int64_t)k0 : (int64_t)k0 * lda);
-    const double* Bk = B + (tb ? (int64_t)k0 * ldb : (int64_t)k0);
-    const hipError_t e = gemm(st, PREC_FP64, ta, tb, M, N, kc, alpha, Ak, lda, Bk, ldb,
-                              k0 == 0 ? beta : 1.0, C, ldc, nullptr, 0, true);
-    if (e != hipSuccess) return e;
-    if (K <= 0) break;
+  for (int n0 = 0; n0 < N; n0 += kSideCols) {
+    const int nc = std::min(kSideCols, N - n0);
+    const double* Bn = B + (tb ? (int64_t)n0 : (int64_t)n0 * ldb);
+    double* Cn = C + (int64_t)n0 * ldc;
+    for (int k0 = 0; k0 < K || k0 == 0; k0 += chunk) {
+      const int kc = std::min(chunk, K - k0);
+      const double* Ak = A + (ta ? (int64_t)k0 : (int64_t)k0 * lda);
+      const double* Bk = Bn + (tb ? (int64_t)k0 * ldb : (int64_t)k0);
+      const hipError_t e = gemm(st, PREC_FP64, ta, tb, M, nc, kc, alpha, Ak, lda, Bk, ldb,
+                                k0 == 0 ? beta : 1.0, Cn, ldc, nullptr, 0, true);
+      if (e != hipSuccess) return e;
+      if (K <= 0) break;
+    }
   }
   return hipSuccess;
 }

@@ -359,7 +359,7 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
                        int64_t strideD, double* Wk, double* Vk, int* status, int max_sweeps) {
   if (count <= 0) return hipSuccess;
   if (ld > MAXN) return hipErrorInvalidValue;
-  const int slot = prof_mark(st);
+  const int slot = prof_mark(st, PC_SVD);
   if (ld > kMaxLdsN) {
     hipLaunchKernelGGL(k_jacobi, dim3(count), dim3(256), 0, st, nb_dev, ld, R, strideR, Us, Vs,
                        strideUV, D, strideD, Wk, Vk, status, max_sweeps);
