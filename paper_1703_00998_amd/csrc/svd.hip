@@ -22,6 +22,7 @@
 // e_1, e_2, ...  Matrices wider than kMaxLdsN use a single-workgroup
 // global-memory kernel.
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 
@@ -34,11 +35,47 @@ constexpr int kRoundThreads = 64 * kBW;  // one wave per column pair of a sub-ro
 constexpr int kMaxLdsN = 256;    // largest order handled by the LDS block kernel
 constexpr int kFirstSweeps = 6;  // block-Jacobi sweeps launched before the first convergence check
 constexpr int kMoreSweeps = 2;   // and between later checks
+constexpr int kMaxPollDevices = 64;
 
+// DPP move of a double (two 32-bit halves) with control CTRL.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+__device__ inline double lane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes of a wave, the same value in every lane.  Called
+// with all lanes active.  Within each row of 16 lanes: butterflies over
+// lane ^ 1, lane ^ 2 (quad_perm), the other quad of the half row
+// (row_half_mirror) and the other half (row_mirror); then the four row
+// sums from lanes 0, 16, 32, 48.  No LDS traffic, unlike a shuffle-based
+// butterfly.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+
+// 1/x and 1/sqrt(x), x > 0 normal: hardware estimates (relative error
+// below 2^-22) and two Newton steps each (quadratic convergence: 2^-44,
+// then below 2^-52 up to rounding).
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * fma(-h * y, y, 1.5);
+  return y * fma(-h * y, y, 1.5);
 }
 
 __device__ inline double jacobi_tol(int nb) { return 4.0 * 2.220446049250313e-16 * sqrt((double)nb); }
@@ -60,11 +97,18 @@ __device__ inline bool rotate_pair(double* wp, double* wq, double* vp, double* v
   ga = wave_sum(ga);
   if (ga == 0.0 || al == 0.0 || be == 0.0) return false;
   if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
-  const double zeta = (be - al) / (2.0 * ga);
+  // Rotation angle (Rutishauser's formulas).  The reciprocals and the
+  // square roots come from the hardware estimates refined by Newton steps
+  // (a few ulp): c and s need not be correctly rounded, only consistent,
+  // and c^2 + s^2 = 1 holds to the accuracy of c.
+  const double zeta = (be - al) * rcp_nr(2.0 * ga);
   double t;
-  if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-  else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+  if (fabs(zeta) > 1e150) t = 0.5 * rcp_nr(zeta);
+  else {
+    const double w = 1.0 + zeta * zeta;
+    t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + w * rsq_nr(w));
+  }
+  const double c = rsq_nr(1.0 + t * t), s = c * t;
   for (int i = lane; i < n; i += 64) {
     const double x = wp[i], y = wq[i];
     wp[i] = c * x - s * y;
@@ -220,11 +264,13 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
     const int g = blk * kBW + (c % kBW);
     return (blk < nblk && g < nb) ? g : -1;
   };
-  for (int idx = tid; idx < 2 * kBW * nb; idx += kRoundThreads) {
-    const int c = idx / nb, i = idx % nb;
+  // Column c of the pair per wave, rows lane-strided (no index division).
+  for (int c = wave; c < 2 * kBW; c += kRoundThreads / 64) {
     const int g = gcol(c);
-    sW[c * ldl + i] = g >= 0 ? W[i + (int64_t)g * ld] : 0.0;
-    sV[c * ldl + i] = g >= 0 ? V[i + (int64_t)g * ld] : 0.0;
+    for (int i = lane; i < nb; i += 64) {
+      sW[c * ldl + i] = g >= 0 ? W[i + (int64_t)g * ld] : 0.0;
+      sV[c * ldl + i] = g >= 0 ? V[i + (int64_t)g * ld] : 0.0;
+    }
   }
   const double tol = jacobi_tol(nb);
   if (tid == 0) srot = 0;
@@ -261,10 +307,10 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
     __syncthreads();
   }
   const bool any = srot != 0;
-  for (int idx = tid; idx < 2 * kBW * nb; idx += kRoundThreads) {
-    const int c = idx / nb, i = idx % nb;
+  for (int c = wave; c < 2 * kBW; c += kRoundThreads / 64) {
     const int g = gcol(c);
-    if (g >= 0) {
+    if (g < 0) continue;
+    for (int i = lane; i < nb; i += 64) {
       W[i + (int64_t)g * ld] = sW[c * ldl + i];
       V[i + (int64_t)g * ld] = sV[c * ldl + i];
     }
@@ -386,11 +432,40 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
   // skips later rounds on the device anyway; this saves the launches.
   // The counts come back through pinned host memory and an event that the
   // host polls (a blocking stream synchronization wakes up milliseconds late).
+  // Pinned buffer and event are kept per device between calls (allocating
+  // pinned memory costs far more than one small SVD); calls that poll on
+  // one device take turns.
+  struct Poll {
+    int* last = nullptr;
+    int cap = 0;
+    hipEvent_t ev = nullptr;
+    std::mutex mu;
+  };
+  static Poll polls[kMaxPollDevices];
+  int dev = 0;
+  const bool dev_ok = hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxPollDevices;
+  std::unique_lock<std::mutex> lock;
   int* last = nullptr;
   hipEvent_t ev = nullptr;
-  bool check = hipHostMalloc((void**)&last, (size_t)count * sizeof(int), hipHostMallocDefault) ==
-                   hipSuccess &&
-               hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+  if (dev_ok) {
+    Poll& pl = polls[dev];
+    lock = std::unique_lock<std::mutex>(pl.mu);
+    if (pl.cap < count) {
+      if (pl.last) (void)hipHostFree(pl.last);
+      pl.last = nullptr;
+      pl.cap = 0;
+      if (hipHostMalloc((void**)&pl.last, (size_t)count * sizeof(int), hipHostMallocDefault) ==
+          hipSuccess)
+        pl.cap = count;
+      else
+        pl.last = nullptr;
+    }
+    if (!pl.ev && hipEventCreateWithFlags(&pl.ev, hipEventDisableTiming) != hipSuccess)
+      pl.ev = nullptr;
+    last = pl.last;
+    ev = pl.ev;
+  }
+  const bool check = last && ev;
   (void)hipGetLastError();
   hipError_t e = hipSuccess;
   for (int sw0 = 0; sw0 < max_sweeps && e == hipSuccess;) {
@@ -413,8 +488,6 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
     for (int i = 0; i < count; ++i) done = done && last[i] == 0;
     if (done) break;
   }
-  if (ev) (void)hipEventDestroy(ev);
-  if (last) (void)hipHostFree(last);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(256), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
                      Vs, D, strideD, rotcount, max_sweeps, status);
