@@ -42,7 +42,7 @@ __all__ = [
     "householder", "house_qr", "apply_right", "apply_left", "small_svd",
     "top_left_singular_vectors",
     "num_steps", "num_random_steps", "g_slab", "randutv", "approx",
-    "approx_jvp", "rsvd", "flops_paper", "flops_uv",
+    "approx_jvp", "rsvd", "randutv_lower", "flops_paper", "flops_uv",
 ]
 
 
@@ -280,6 +280,18 @@ def randutv(A, b, q, G, *, p=0, form_u=True, form_v=True, k_stop=0, tol=0.0,
             if form_v:
                 V[:, r0:] = V[:, r0:] @ Vs
     return U, T, V, k_done
+
+
+# --------------------------------------------------------------------------
+# Section 1 (the middle factor may be taken lower triangular): A = U L V^T.
+# --------------------------------------------------------------------------
+def randutv_lower(A, b, q, G, **kw):
+    """[U, L, V, k] with L lower triangular, from randUTV of A^T:
+    A^T = U' T V'^T gives A = V' T^T U'^T, so U = V', L = T^T, V = U'.
+    G is the packed Gaussian of the n x m problem (n rows).  k counts the
+    leading rows of L in lower-triangular form."""
+    U1, T1, V1, k = randutv(np.asarray(A).T, b, q, G, **kw)
+    return V1, T1.T.copy(), U1, k
 
 
 # --------------------------------------------------------------------------

@@ -582,3 +582,42 @@ def test_rsvd_range_matches_randutv_first_step():
     e = np.linalg.norm(A - (U * D) @ V.T)
     assert abs(e - np.linalg.norm(T[:, b:])) <= 1e-12 * e
     np.testing.assert_allclose(D, np.diag(T)[:b], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Lower-triangular middle factor (Section 1: upper or lower, as preferred).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,b,q", [((60, 40), 8, 1), ((40, 60), 8, 1), ((50, 50), 16, 2)])
+def test_lower_variant_invariants(shape, b, q):
+    """A = U L V^T with U, V orthogonal, L lower triangular with diagonal
+    blocks, its diagonal nonnegative and descending inside each block, and
+    Ky Fan's bound on the leading diagonal entries."""
+    m, n = shape
+    sig = np.exp(-np.arange(1, min(m, n) + 1) / 6.0)
+    A = wl.planted(m, n, sig, seed=3)
+    G = wl.gaussian_g(n, m, b, seed=1)
+    U, L, V, k = ref.randutv_lower(A, b, q, G)
+    assert k == min(m, n)
+    assert np.linalg.norm(A - U @ L @ V.T) <= 1e-13 * np.linalg.norm(A)
+    assert np.linalg.norm(U.T @ U - np.eye(m)) <= 1e-13 and np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-13
+    assert np.all(np.triu(L, 1) == 0.0)
+    d = np.diag(L)
+    for s0 in range(0, min(m, n), b):
+        blk = L[s0:s0 + b, s0:s0 + b]
+        assert np.all(blk - np.diag(np.diag(blk)) == 0.0)
+        db = d[s0:s0 + b]
+        assert np.all(db >= 0) and np.all(np.diff(db) <= 0)
+    assert np.all(np.cumsum(d ** 2) <= np.cumsum(sig ** 2) * (1 + 1e-12))
+
+
+def test_lower_variant_b_ge_min_is_svd():
+    """b >= min(m, n): one step, the final SVD, so L = [diag(sigma), 0] and
+    U L V^T is an SVD of A."""
+    sig = np.array([3.0, 2.0, 1.5, 0.7, 0.2])
+    A = wl.planted(9, 5, sig, seed=4)
+    G = wl.gaussian_g(5, 9, 8, seed=1)
+    U, L, V, k = ref.randutv_lower(A, 8, 1, G)
+    np.testing.assert_allclose(np.diag(L), sig, rtol=1e-13)
+    assert np.linalg.norm(L[:5, :5] - np.diag(sig)) <= 1e-13 * 3
+    assert np.linalg.norm(L[5:, :]) == 0.0
+    assert np.linalg.norm(A - U @ L @ V.T) <= 1e-13 * 3
