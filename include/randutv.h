@@ -130,6 +130,35 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q,
                    int64_t* k_out, void* stream);
 
 /*
+ * randutv_factor_lower -- the same factorization with a lower-triangular
+ * middle factor, A = U L V^T (Section 1: the middle factor may be taken
+ * upper or lower triangular).  Computed as randutv_factor of A^T
+ * (A^T = U' T V'^T, so U = V', L = T^T, V = U'), with A^T formed in the
+ * workspace by a tiled transpose and L transposed back into T.
+ * Arguments as randutv_factor except:
+ *  4  T, ldt   in: A (m x n).  out: L, lower triangular in its first k rows
+ *              (exact zeros above the diagonal and off the diagonal inside
+ *              each diagonal block; the diagonal >= 0 and descending within
+ *              each block).
+ *  5  G, ldg   packed N(0,1) matrix of the n x m problem:
+ *              n x randutv_g_cols(n, m, b), ldg >= n.
+ * 12  work     randutv_workspace_size_lower() bytes.
+ * Statuses as randutv_factor (argument numbers of this call), except that
+ * a HIP or numerical status from the inner factorization is passed on.
+ */
+int randutv_workspace_size_lower(int64_t m, int64_t n, int64_t b, int q,
+                                 int prec, unsigned flags, size_t* bytes);
+int randutv_factor_lower(int64_t m, int64_t n, int64_t b, int q,
+                         double* T, int64_t ldt,
+                         const double* G, int64_t ldg,
+                         double* U, int64_t ldu,
+                         double* V, int64_t ldv,
+                         int64_t k_stop, double tol,
+                         int prec, unsigned flags,
+                         void* work, size_t work_bytes,
+                         int64_t* k_out, void* stream);
+
+/*
  * Over-sampled variants (Remark on over-sampling, Section 5.3; Appendix A.2,
  * the over-sampled step): each randomized step draws b + p samples,
  * Y = (X^T X)^q X^T G_i with G_i of b + p columns, and the Householder QR is

@@ -49,6 +49,11 @@ def lib():
     L.randutv_factor.argtypes = [i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, i64,
                                  i64, dbl, i32, u32, vp, sz, ctypes.POINTER(i64), vp]
     L.randutv_factor.restype = i32
+    L.randutv_workspace_size_lower.argtypes = [i64, i64, i64, i32, i32, u32, ctypes.POINTER(sz)]
+    L.randutv_workspace_size_lower.restype = i32
+    L.randutv_factor_lower.argtypes = [i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, i64,
+                                       i64, dbl, i32, u32, vp, sz, ctypes.POINTER(i64), vp]
+    L.randutv_factor_lower.restype = i32
     L.randutv_g_cols_p.argtypes = [i64, i64, i64, i64]
     L.randutv_g_cols_p.restype = i64
     L.randutv_workspace_size_p.argtypes = [i64, i64, i64, i64, i32, i32, u32,
@@ -103,7 +108,7 @@ def lib():
 
 EXPORTS = ["randutv_random_steps", "randutv_g_cols", "randutv_workspace_size",
            "randutv_factor", "randutv_g_cols_p", "randutv_workspace_size_p", "randutv_factor_p",
-           "randutv_rsvd_workspace_size", "randutv_rsvd", "randutv_gemm",
+           "randutv_workspace_size_lower", "randutv_factor_lower", "randutv_rsvd_workspace_size", "randutv_rsvd", "randutv_gemm",
            "randutv_panel_work_size", "randutv_panel_qr",
            "randutv_small_svd_work_size", "randutv_small_svd", "randutv_strerror",
            "randutv_profile_begin", "randutv_profile_begin_class", "randutv_profile_end", "randutv_profile_class_name",
@@ -247,6 +252,41 @@ def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", w
             m, n, b, q, _ptr(T), ldt, gp, ldg, _ptr(U), ldu, _ptr(V), ldv, int(k_stop),
             float(tol), PREC[prec], flags, wp, wbytes, kp, _stream())
         _check(st, "randutv_factor")
+    return int(k.value) if (sync or tol > 0) else None
+
+
+def workspace_size_lower(m, n, b, q=1, prec="fp64", form_u=True, form_v=True):
+    flags = (FORM_U if form_u else 0) | (FORM_V if form_v else 0)
+    out = ctypes.c_size_t(0)
+    _check(lib().randutv_workspace_size_lower(m, n, b, q, PREC[prec], flags, ctypes.byref(out)),
+           "randutv_workspace_size_lower")
+    return int(out.value)
+
+
+def randutv_factor_lower(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64",
+                         work=None, sync=True):
+    """In-place A = U L V^T with L lower triangular (T: m x n column-major
+    FP64, overwritten by L); G is the n x g_cols(n, m, b) Gaussian of the
+    transposed problem.  Returns k when sync=True."""
+    m, n = T.shape
+    ldt = _ld(T, m)
+    gc = g_cols(n, m, b)
+    ldg = _ld(G, n) if (G is not None and G.numel() > 0) else max(n, 1)
+    if gc > 0 and (G is None or G.shape[1] < gc):
+        raise RandUTVError(f"G needs {gc} columns")
+    ldu = _ld(U, m) if U is not None else m
+    ldv = _ld(V, n) if V is not None else n
+    flags = (FORM_U if U is not None else 0) | (FORM_V if V is not None else 0)
+    if work is None:
+        work = workspace(workspace_size_lower(m, n, b, q, prec, U is not None, V is not None),
+                         T.device)
+    wp, wbytes = _aligned_ptr(work)
+    k = ctypes.c_int64(0)
+    st = lib().randutv_factor_lower(
+        m, n, b, q, _ptr(T), ldt, _ptr(G) if gc > 0 else ctypes.c_void_p(0), ldg, _ptr(U), ldu,
+        _ptr(V), ldv, int(k_stop), float(tol), PREC[prec], flags, wp, wbytes,
+        ctypes.byref(k) if (sync or tol > 0) else None, _stream())
+    _check(st, "randutv_factor_lower")
     return int(k.value) if (sync or tol > 0) else None
 
 

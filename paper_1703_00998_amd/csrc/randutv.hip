@@ -195,6 +195,34 @@ __global__ void k_transpose(int M, int N, const double* __restrict__ A, int64_t 
   }
 }
 
+// B = A^T for the M x N matrix A through 32 x 32 LDS tiles (coalesced reads
+// and writes); the whole-matrix transposes of the lower-triangular variant.
+constexpr int kTT = 32;
+__global__ __launch_bounds__(256) void k_transpose_tiled(int M, int N, const double* __restrict__ A,
+                                                         int64_t lda, double* __restrict__ Bt,
+                                                         int64_t ldb) {
+  __shared__ double t[kTT][kTT + 1];
+  const int i0 = blockIdx.x * kTT, j0 = blockIdx.y * kTT;
+  const int tx = threadIdx.x % kTT, ty = threadIdx.x / kTT;
+  for (int jj = ty; jj < kTT; jj += 256 / kTT) {
+    const int i = i0 + tx, j = j0 + jj;
+    if (i < M && j < N) t[jj][tx] = A[i + (int64_t)j * lda];
+  }
+  __syncthreads();
+  for (int ii = ty; ii < kTT; ii += 256 / kTT) {
+    const int j = j0 + tx, i = i0 + ii;
+    if (i < M && j < N) Bt[j + (int64_t)i * ldb] = t[tx][ii];
+  }
+}
+
+hipError_t transpose(hipStream_t st, int M, int N, const double* A, int64_t lda, double* Bt,
+                     int64_t ldb) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_tiled, dim3((M + kTT - 1) / kTT, (N + kTT - 1) / kTT),
+                     dim3(256), 0, st, M, N, A, lda, Bt, ldb);
+  return hipGetLastError();
+}
+
 __global__ void k_set_ints(int* p, int count, int v, int last) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = (i == count - 1) ? last : v;
 }
@@ -293,6 +321,23 @@ int randutv_workspace_size_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, 
   return 0;
 }
 
+// flags of the transposed problem: U of A^T is V of A and vice versa.
+inline unsigned swap_uv(unsigned flags) {
+  return (flags & RANDUTV_FORM_U ? RANDUTV_FORM_V : 0u) | (flags & RANDUTV_FORM_V ? RANDUTV_FORM_U : 0u);
+}
+
+int randutv_workspace_size_lower(int64_t m, int64_t n, int64_t b, int q, int prec, unsigned flags,
+                                 size_t* bytes) {
+  if (n < 1 || m < 1) return -1;
+  if (b < 1 || b > kMaxB) return -3;
+  if (q < 0 || q > 16) return -4;
+  if (prec < 0 || prec > 3) return -5;
+  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -6;
+  if (!bytes) return -7;
+  *bytes = al256((size_t)m * n * sizeof(double)) + make_layout(n, m, b).total;
+  return 0;
+}
+
 int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, unsigned flags,
                            size_t* bytes) {
   if (n < 1 || m < 1) return -1;
@@ -322,6 +367,38 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ld
                    void* work, size_t work_bytes, int64_t* k_out, void* stream) {
   return rutv::factor_impl(m, n, b, q, T, ldt, G, ldg, U, ldu, V, ldv, k_stop, tol, prec, flags,
                            work, work_bytes, k_out, stream, nullptr);
+}
+
+int randutv_factor_lower(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt,
+                         const double* G, int64_t ldg, double* U, int64_t ldu, double* V,
+                         int64_t ldv, int64_t k_stop, double tol, int prec, unsigned flags,
+                         void* work, size_t work_bytes, int64_t* k_out, void* stream) {
+  if (m < 1 || n < 1) return -1;
+  if (std::max(m, n) > kMaxPanelRows || m * n > ((int64_t)1 << 40)) return RANDUTV_E_UNSUPPORTED;
+  if (b < 1 || b > kMaxB) return -2;
+  if (q < 0 || q > 16) return -3;
+  if (!T || ldt < m) return -4;
+  if (randutv_g_cols(n, m, b) > 0 && (!G || ldg < n)) return -5;
+  if ((flags & RANDUTV_FORM_U) && (!U || ldu < m)) return -6;
+  if ((flags & RANDUTV_FORM_V) && (!V || ldv < n)) return -7;
+  if (prec < 0 || prec > 3) return -10;
+  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -11;
+  if (!work || ((uintptr_t)work & 255)) return -12;
+  size_t need = 0;
+  randutv_workspace_size_lower(m, n, b, q, prec, flags, &need);
+  if (work_bytes < need) return RANDUTV_E_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  double* Tt = (double*)work;  // A^T, n x m
+  const size_t tb = al256((size_t)m * n * sizeof(double));
+  HIPCHK(transpose(st, (int)m, (int)n, T, ldt, Tt, n));
+  // A^T = U' T' V'^T, so A = V' T'^T U'^T: U of A^T goes to V, V of A^T to U.
+  const int r = rutv::factor_core(n, m, b, 0, q, Tt, n, G, ldg, V, ldv, U, ldu, k_stop, tol, prec,
+                                  swap_uv(flags), (char*)work + tb, work_bytes - tb, k_out, stream,
+                                  nullptr);
+  if (r < 0) return r;
+  HIPCHK(transpose(st, (int)n, (int)m, Tt, n, T, ldt));
+  if (k_out) HIPCHK(hipStreamSynchronize(st));
+  return r;
 }
 
 int randutv_factor_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,

@@ -166,3 +166,26 @@ def test_rsvd_entry_points_validate(lib):
     assert call(ldv=199) == -13
     assert call() == -16
     assert call(work=vp(4096), wb=16) == -901
+
+
+def test_lower_entry_points_validate(lib):
+    sz = ctypes.c_size_t(0)
+    assert lib.randutv_workspace_size_lower(100, 80, 16, 1, 0, 3, ctypes.byref(sz)) == 0
+    s0 = ctypes.c_size_t(0)
+    assert lib.randutv_workspace_size(80, 100, 16, 1, 0, 3, ctypes.byref(s0)) == 0
+    assert sz.value >= s0.value + 100 * 80 * 8     # A^T plus the transposed problem's workspace
+    assert lib.randutv_workspace_size_lower(100, 80, 0, 1, 0, 3, ctypes.byref(sz)) == -3
+    vp = ctypes.c_void_p
+    null = vp(0)
+    fake = vp(1 << 20)  # never dereferenced: validation fails first
+
+    def call(T=fake, ldt=100, G=fake, ldg=80, flags=0, work=null, wb=0, b=16):
+        return lib.randutv_factor_lower(100, 80, b, 1, T, ldt, G, ldg, null, 100, null, 80, 0,
+                                        0.0, 0, flags, work, wb, None, null)
+    assert call(b=0) == -2
+    assert call(T=null) == -4
+    assert call(ldg=79) == -5        # G has n = 80 rows
+    assert call(flags=1) == -6
+    assert call(flags=2) == -7
+    assert call() == -12
+    assert call(work=vp(4096), wb=16) == -901
