@@ -63,21 +63,6 @@ __device__ inline double wave_sum(double v) {
   return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
-// 1/x and 1/sqrt(x), x > 0 normal: hardware estimates (relative error
-// below 2^-22) and two Newton steps each (quadratic convergence: 2^-44,
-// then below 2^-52 up to rounding).
-__device__ inline double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
-__device__ inline double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  y = y * fma(-h * y, y, 1.5);
-  return y * fma(-h * y, y, 1.5);
-}
-
 __device__ inline double jacobi_tol(int nb) { return 4.0 * 2.220446049250313e-16 * sqrt((double)nb); }
 
 // Rotate columns (wp, wq) of W and (vp, vq) of V so that wp^T wq = 0, if
@@ -97,18 +82,11 @@ __device__ inline bool rotate_pair(double* wp, double* wq, double* vp, double* v
   ga = wave_sum(ga);
   if (ga == 0.0 || al == 0.0 || be == 0.0) return false;
   if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
-  // Rotation angle (Rutishauser's formulas).  The reciprocals and the
-  // square roots come from the hardware estimates refined by Newton steps
-  // (a few ulp): c and s need not be correctly rounded, only consistent,
-  // and c^2 + s^2 = 1 holds to the accuracy of c.
-  const double zeta = (be - al) * rcp_nr(2.0 * ga);
+  const double zeta = (be - al) / (2.0 * ga);
   double t;
-  if (fabs(zeta) > 1e150) t = 0.5 * rcp_nr(zeta);
-  else {
-    const double w = 1.0 + zeta * zeta;
-    t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + w * rsq_nr(w));
-  }
-  const double c = rsq_nr(1.0 + t * t), s = c * t;
+  if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+  else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
   for (int i = lane; i < n; i += 64) {
     const double x = wp[i], y = wq[i];
     wp[i] = c * x - s * y;
