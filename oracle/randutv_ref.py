@@ -27,6 +27,10 @@ design notes of the repository):
     T(:,[J2,J3]) = T(:,[J2,J3]) V).
   * Early stop: after step i, stop when ||T(I3,J3)||_F <= tol*||A||_F or when
     (i+1)*b >= k_stop (Section 1.1, advantage (ii)).
+  * Lower-triangular middle factor (`randutv_lower`): randUTV of A^T,
+    transposed.
+  * Randomized SVD (`rsvd`, Remark RSVD): the b dominant triplets of the
+    rank-(b+p) factorization when over-sampling; signs as for the small SVDs.
 
 All routines are written without complex conjugation (``x @ x`` instead of
 ``|x|^2``, ``.T`` instead of ``.conj().T``, branch decisions on ``.real``) so

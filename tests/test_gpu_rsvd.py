@@ -44,8 +44,10 @@ def _case(m, n, k, p, decay):
     return A, G, sig
 
 
+# The last two: k + p = min(m, n) (Y and B's QRs are square) and k = 1.
 CASES = [(300, 200, 20, 0, 1), (500, 400, 32, 8, 1), (257, 300, 40, 10, 2),
-         (1000, 700, 128, 0, 0), (600, 600, 120, 20, 1), (800, 600, 200, 56, 1)]
+         (1000, 700, 128, 0, 0), (600, 600, 120, 20, 1), (800, 600, 200, 56, 1),
+         (300, 200, 150, 50, 1), (120, 90, 1, 0, 1)]
 
 
 @pytest.mark.parametrize("m,n,k,p,q", CASES)
