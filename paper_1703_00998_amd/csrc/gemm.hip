@@ -409,7 +409,15 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   if (splitws && tiles < 512 && K >= 1024) {
     // Small outputs (Gram matrices of tall panels) split deeper.
     const bool small = tiles <= 32;
-    splits = ((small ? 1024 : 512) + tiles - 1) / tiles;
+    // 128 x 128 tiles in BF16x3 or FP64 fit two workgroups per CU (LDS):
+    // at most 512 workgroups, rounded down, so that all of them run in one
+    // wave instead of a full wave and a short second one (126 tiles of the
+    // thin sampling products: 4 splits, not 5).  Otherwise about 512,
+    // rounded up (FP32 128 x 128 and 64 x 64 tiles fit more per CU, and the
+    // FP32 products keep their shorter FP32 accumulation chains).
+    const bool two_per_cu = shape == 1 && (prec == PREC_BF16X3 || prec == PREC_FP64);
+    splits = small ? (1024 + tiles - 1) / tiles
+                   : (two_per_cu ? std::max(1, 512 / tiles) : (512 + tiles - 1) / tiles);
     splits = std::min(splits, K / (small ? 256 : 512));
     splits = std::min(splits, small ? kMaxSplitKSmall : kMaxSplitK);
     while (splits > 1 && (size_t)splits * M * N > splitws_elems) --splits;
