@@ -18,7 +18,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -295,7 +294,7 @@ def oversample_run(B, torch, wl):
         return {"error": repr(e)}
 
 
-def lower_run(B, torch, wl, dA, sig):
+def lower_run(B, torch, wl, dA):
     """Lower-triangular variant (A = U L V^T, randUTV of A^T; Section 1) on the
     8000 x 8000 workload, b = 256, q = 1, U and V formed, headline split path:
     time per factorization including the two tiled transposes, residual."""
@@ -637,7 +636,7 @@ def main():
         out["wide_4000x8000"] = wide_run(B, torch, wl)
         out["oversample_4000"] = oversample_run(B, torch, wl)
         out["rsvd_8000"] = rsvd_run(B, torch, wl, dA, sig)
-        out["lower_8000"] = lower_run(B, torch, wl, dA, sig)
+        out["lower_8000"] = lower_run(B, torch, wl, dA)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_n}x{args.cpu_n} sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, b, q)
