@@ -2,20 +2,23 @@
 //
 // Per randomized step i (r0 = i*b, X = T(r0:m, r0:n)):
 //   Y = X^T G_i; q times: Z = X Y, Y = X^T Z            (thin MFMA GEMMs)
-//   Householder QR of Y -> Vh, tau, Tw_V                 (cooperative panel)
+//   [p > 0: Y <- its b dominant left singular vectors]   (over-sampling)
+//   Householder QR of Y -> Vh, tau, Tw_V                 (panel_qr_hr)
 //   T(:, r0:n) <- T(:, r0:n) (I - Vh Tw_V Vh^T)          (all m rows)
-//   V(:, r0:n) likewise                                  (if formed)
-//   Householder QR of T(r0:m, r0:r0+b) -> Uh, Tw_U, R    (cooperative panel)
+//   V(:, r0:n) likewise                                  (second stream)
+//   Householder QR of T(r0:m, r0:r0+b) -> Uh, Tw_U, R    (panel_qr_hr)
 //   T(r0:m, r0+b:n) <- (I - Uh Tw_U Uh^T)^T T(...)
-//   U(:, r0:m) <- U(:, r0:m) (I - Uh Tw_U Uh^T)          (if formed)
+//   U(:, r0:m) <- U(:, r0:m) (I - Uh Tw_U Uh^T)          (second stream)
 //   T(r0:m, r0:r0+b) <- 0, R stashed
 // The last block (I3 or J3 empty) takes the economic path of the Remark on
-// tall SVDs: Householder QR, then the SVD of its square R.
+// tall SVDs: Householder QR, then the SVD of its square R; with fewer rows
+// than columns, an LQ of the block row (the Remark on the case m < n).
 // The b x b SVDs do not feed later steps: step i's rotations act only on
 // block row i (from the left), block column i (from the right) and columns
 // of U and V that later steps never touch, and left and right
-// multiplications commute.  So all SVDs run batched after the loop, one
-// workgroup each, and their rotations are folded back then.
+// multiplications commute.  So all SVDs run batched after the loop (block
+// Jacobi, every matrix at once) and their rotations are folded back then.
+// The lower-triangular form A = U L V^T runs this on A^T.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
