@@ -4,6 +4,9 @@
 // randUTV factors two tall panels per step (the sampling matrix Y and the
 // updated column block T([I2,I3],J2)); their flops are negligible but the
 // b reflectors form a sequential chain, so the panel is latency-bound.
+// The factorization normally takes the CholeskyQR2 + Householder
+// reconstruction path (panel_hr.hip); the kernels here are its fallback
+// for panels that path declines, launched gated on its device flag.
 //
 // Design: one cooperative launch.  Each of `nwg` workgroups owns a slab of
 // consecutive rows.  Columns are taken in sub-panels of kPanelNB; the
