@@ -37,7 +37,8 @@ constexpr int kMaxPanelRows = kPanelMaxWGGlobal * kPanelMaxRows;
 constexpr int kJacobiSweeps = 40;
 
 struct Layout {
-  size_t Y, Vh, Vh2, Z, Uh, Uh2, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwU, TwU2, tauV, tauU, Rst,
+  size_t Y, Vh, Vh2, Vh3, Z, Uh, Uh2, Uh3, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwV3, TwU, TwU2,
+      TwU3, tauV, tauU, Rst,
       Ust, Vst, D, Jw, Jv, Ftmp, split, nrm, ints, panel, hr, total;
   // Over-sampling (p > 0) only: QR and SVD of the extended sample.
   size_t VY, TwY, RY, UR, VR, JwR, JvR, tauY, DR, Cy, Cy2, intsY;
@@ -70,9 +71,11 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   L.Y = take((size_t)n * bp * d);
   L.Vh = take(nb * d);
   L.Vh2 = take(nb * d);
+  L.Vh3 = take(nb * d);
   L.Z = take((size_t)m * bp * d);
   L.Uh = take(mb * d);
   L.Uh2 = take(mb * d);
+  L.Uh3 = take(mb * d);
   L.W = take(mb * d);
   L.W2 = take(mb * d);
   L.Ws = take(std::max(mb, nb) * d);   // U / V stream products, leading dimension max(m, n)
@@ -81,8 +84,10 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   L.C2 = take(nb * d);
   L.TwV = take(bb * d);
   L.TwV2 = take(bb * d);
+  L.TwV3 = take(bb * d);
   L.TwU = take(bb * d);
   L.TwU2 = take(bb * d);
+  L.TwU3 = take(bb * d);
   L.tauV = take(b * d);
   L.tauU = take(b * d);
   L.Rst = take(s * bb * d);
@@ -117,15 +122,21 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   return L;
 }
 
+// Reflector slots shared with the U / V stream (step i uses slot i % kSlots).
+constexpr int kSlots = 3;
+
 // U and V accumulation runs on a second stream of the device (default
 // priority), ordered against the main stream by events: the panels and
 // small products of the main chain are latency-bound and leave most of the
 // chip idle, which the FP64 U / V block-reflector products fill.  Step i
-// uses reflector slot i % 2; the main stream waits for the side stream to
-// release a slot before overwriting it.
+// uses reflector slot i % kSlots; the main stream waits for the side stream
+// to release a slot before overwriting it (three slots let the side stream
+// fall two steps behind without stalling the main one: 126-127 ms per
+// 8000 x 8000 factorization against 127.5-128.4 ms with two).
 struct SideCtx {
   hipStream_t side = nullptr;
-  hipEvent_t ev[9] = {};  // V ready[2], U ready[2], V done[2], U done[2], join
+  // V ready, U ready, V done, U done (kSlots each), join.
+  hipEvent_t ev[4 * kSlots + 1] = {};
   bool ok = false;
 };
 constexpr int kMaxDevices = 64;
@@ -475,20 +486,21 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   int* intsY = p > 0 ? (int*)(base + L.intsY) : nullptr;
   int nrand = 0;  // randomized steps taken
 
-  double* const VhS[2] = {dp(L.Vh), dp(L.Vh2)};
-  double* const UhS[2] = {dp(L.Uh), dp(L.Uh2)};
-  double* const TwVS[2] = {dp(L.TwV), dp(L.TwV2)};
-  double* const TwUS[2] = {dp(L.TwU), dp(L.TwU2)};
+  double* const VhS[kSlots] = {dp(L.Vh), dp(L.Vh2), dp(L.Vh3)};
+  double* const UhS[kSlots] = {dp(L.Uh), dp(L.Uh2), dp(L.Uh3)};
+  double* const TwVS[kSlots] = {dp(L.TwV), dp(L.TwV2), dp(L.TwV3)};
+  double* const TwUS[kSlots] = {dp(L.TwU), dp(L.TwU2), dp(L.TwU3)};
+  constexpr int kVR = 0, kUR = kSlots, kVD = 2 * kSlots, kUD = 3 * kSlots, kJoin = 4 * kSlots;
 
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pw.err);
   if (formU) HIPCHK(set_identity(st, M, M, U, ldu));
   if (formV) HIPCHK(set_identity(st, N, N, V, ldv));
   SideCtx* sc = (formU || formV) ? side_ctx() : nullptr;
   const hipStream_t ss = sc ? sc->side : st;  // U / V stream (the main one if none)
-  bool vpend[2] = {false, false}, upend[2] = {false, false};
+  bool vpend[kSlots] = {}, upend[kSlots] = {};
   if (sc) {
-    HIPCHK(hipEventRecord(sc->ev[8], st));
-    HIPCHK(hipStreamWaitEvent(ss, sc->ev[8], 0));
+    HIPCHK(hipEventRecord(sc->ev[kJoin], st));
+    HIPCHK(hipStreamWaitEvent(ss, sc->ev[kJoin], 0));
   }
   // Hand the reflectors of one side to the U / V stream and back.
   auto to_side = [&](int ready) -> hipError_t {
@@ -520,7 +532,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     const int r0 = (int)(i * b);
     const int Mi = M - r0, Ni = N - r0;
     double* X = T + r0 + (int64_t)r0 * ldt;
-    const int sl = (int)(i & 1);
+    const int sl = (int)(i % kSlots);
     double *Vh = VhS[sl], *Uh = UhS[sl], *TwV = TwVS[sl], *TwU = TwUS[sl];
     double *RV = nullptr, *RU = Rst + (size_t)i * B * B;
     if (tape) {  // reflectors and R factors of this step go to the tape
@@ -543,7 +555,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
                                          hw, pw, split, se));
       ++nrand;
       // [Vq, ~] = qr(Y)
-      HIPCHK(reclaim(4 + sl, vpend[sl]));
+      HIPCHK(reclaim(kVD + sl, vpend[sl]));
       HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, RV, B, tauV, TwV, B, hw, pw, split, se));
       // T(:, J) = T(:, J) Vq, all m rows.
       double* TJ = T + (int64_t)r0 * ldt;
@@ -552,15 +564,15 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       HIPCHK(gemm(st, pu, false, true, M, Ni, B, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
       if (formV) {  // V(:, J) = V(:, J) Vq, on the U / V stream
         double* VJ = V + (int64_t)r0 * ldv;
-        HIPCHK(to_side(0 + sl));
+        HIPCHK(to_side(kVR + sl));
         HIPCHK(gemm_side(ss, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, MN, kSideChunk));
         HIPCHK(gemm(ss, PREC_FP64, false, false, N, B, B, 1.0, Ws, MN, TwV, B, 0.0, W2s, MN, nullptr, 0));
         HIPCHK(gemm_side(ss, false, true, N, Ni, B, -1.0, W2s, MN, Vh, N, 1.0, VJ, ldv, kSideChunkUpd));
-        HIPCHK(side_done(4 + sl, &vpend[sl]));
+        HIPCHK(side_done(kVD + sl, &vpend[sl]));
       }
       // [Uq, R] = qr(T([I2,I3], J2))
       // (The panel is read in place; T([I2,I3], J2) is overwritten below.)
-      HIPCHK(reclaim(6 + sl, upend[sl]));
+      HIPCHK(reclaim(kUD + sl, upend[sl]));
       HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, M, RU, B, tauU, TwU, B, hw, pw, split, se));
       // T([I2,I3], J3) = Uq^T T([I2,I3], J3)
       const int Nr = Ni - B;
@@ -571,11 +583,11 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       // U(:, [I2,I3]) = U(:, [I2,I3]) Uq
       if (formU) {  // on the U / V stream
         double* UI = U + (int64_t)r0 * ldu;
-        HIPCHK(to_side(2 + sl));
+        HIPCHK(to_side(kUR + sl));
         HIPCHK(gemm_side(ss, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, kSideChunk));
         HIPCHK(gemm(ss, PREC_FP64, false, false, M, B, B, 1.0, Ws, MN, TwU, B, 0.0, W2s, MN, nullptr, 0));
         HIPCHK(gemm_side(ss, false, true, M, Mi, B, -1.0, W2s, MN, Uh, M, 1.0, UI, ldu, kSideChunkUpd));
-        HIPCHK(side_done(6 + sl, &upend[sl]));
+        HIPCHK(side_done(kUD + sl, &upend[sl]));
       }
       // T([I2,I3], J2) = [R; 0]; R moves to the stash, the diagonal block is
       // written from the SVD after the loop.
@@ -605,7 +617,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       hipLaunchKernelGGL(k_transpose, dim3(grid_blocks((int64_t)Mi * Ni)), dim3(256), 0, st, Mi,
                          Ni, X, ldt, Y, (int64_t)N);
       HIPCHK(hipGetLastError());
-      HIPCHK(reclaim(4 + sl, vpend[sl]));
+      HIPCHK(reclaim(kVD + sl, vpend[sl]));
       HIPCHK(panel_qr_hr(st, Ni, c, Y, N, Vh, N, Ftmp, c, tauV, TwV, B, hw, pw, split, se));
       hipLaunchKernelGGL(k_transpose, dim3(grid_blocks((int64_t)c * c)), dim3(256), 0, st, c, c,
                          Ftmp, (int64_t)c, RU, (int64_t)B);
@@ -617,11 +629,11 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       }
       if (formV) {  // V(:, J) = V(:, J) H, on the U / V stream
         double* VJ = V + (int64_t)r0 * ldv;
-        HIPCHK(to_side(0 + sl));
+        HIPCHK(to_side(kVR + sl));
         HIPCHK(gemm(ss, PREC_FP64, false, false, N, c, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, MN, nullptr, 0));
         HIPCHK(gemm(ss, PREC_FP64, false, false, N, c, c, 1.0, Ws, MN, TwV, B, 0.0, W2s, MN, nullptr, 0));
         HIPCHK(gemm(ss, PREC_FP64, false, true, N, Ni, c, -1.0, W2s, MN, Vh, N, 1.0, VJ, ldv, nullptr, 0));
-        HIPCHK(side_done(4 + sl, &vpend[sl]));
+        HIPCHK(side_done(kVD + sl, &vpend[sl]));
       }
       HIPCHK(set_zero(st, Mi, Ni, X, ldt));
       widths.push_back(c);
@@ -629,16 +641,16 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     } else {
       // Last block: economic SVD via Householder QR of T([I2,I3],[J2,J3]).
       const int c = Ni;
-      HIPCHK(reclaim(6 + sl, upend[sl]));
+      HIPCHK(reclaim(kUD + sl, upend[sl]));
       HIPCHK(panel_qr_hr(st, Mi, c, X, ldt, Uh, M, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
                          pw, split, se));
       if (formU) {
         double* UI = U + (int64_t)r0 * ldu;
-        HIPCHK(to_side(2 + sl));
+        HIPCHK(to_side(kUR + sl));
         HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, nullptr, 0));
         HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, c, 1.0, Ws, MN, TwU, B, 0.0, W2s, MN, nullptr, 0));
         HIPCHK(gemm(ss, PREC_FP64, false, true, M, Mi, c, -1.0, W2s, MN, Uh, M, 1.0, UI, ldu, nullptr, 0));
-        HIPCHK(side_done(6 + sl, &upend[sl]));
+        HIPCHK(side_done(kUD + sl, &upend[sl]));
       }
       HIPCHK(set_zero(st, Mi, c, X, ldt));
       widths.push_back(c);
@@ -648,8 +660,8 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
 
   auto join_side = [&]() -> hipError_t {
     if (!sc) return hipSuccess;
-    hipError_t e = hipEventRecord(sc->ev[8], ss);
-    return e == hipSuccess ? hipStreamWaitEvent(st, sc->ev[8], 0) : e;
+    hipError_t e = hipEventRecord(sc->ev[kJoin], ss);
+    return e == hipSuccess ? hipStreamWaitEvent(st, sc->ev[kJoin], 0) : e;
   };
   if (tape) {  // truncated approximation: no small SVDs (U_k U_k^T does not see them)
     HIPCHK(join_side());
