@@ -26,13 +26,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "randUTV time & eff. TFLOP/s, n=8000 b=256: split-precision vs FP64, same err"
-# Dense MFMA peaks per arithmetic of a GEMM class (BF16x3 issues three BF16
-# MFMAs per product; its class is priced against the BF16 peak).
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
-ERR_BOUND = {"fp64": 1e-13, "fp32": 1e-6, "bf16x3": 1e-6, "bf16x3_fp32": 1e-6}
+# Dense MFMA peaks per arithmetic of a GEMM class (BF16x3 and BF16x6 issue
+# three and six BF16 MFMAs per product; their classes are priced against the
+# BF16 peak).
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+BF16_PRODUCTS = {"bf16x3": 3.0, "bf16x6": 6.0}
+ERR_BOUND = {"fp64": 1e-13, "fp32": 1e-6, "bf16x3": 1e-6, "bf16x3_fp32": 1e-6,
+             "bf16x3_bf16x6": 1e-6}
 DTYPE = {"fp64": "f64", "fp32": "f32 GEMMs (f64 panels/SVD/U,V)",
          "bf16x3": "bf16x3 GEMMs, f32 acc (f64 panels/SVD/U,V)",
-         "bf16x3_fp32": "bf16x3 sampling + f32 updates (f64 panels/SVD/U,V)"}
+         "bf16x3_fp32": "bf16x3 sampling + f32 updates (f64 panels/SVD/U,V)",
+         "bf16x3_bf16x6": "bf16x3 sampling + bf16x6 updates, f32 acc (f64 panels/SVD/U,V)"}
 PRECS = list(ERR_BOUND)
 
 
@@ -113,24 +117,56 @@ def cpu_baseline(n_sample, b, q):
                       f"{f / 1e9:.1f} GFLOP algorithmic"}
 
 
-# Kernel classes also launched inside the panel factorizations, which are
-# timed as a whole under panel_qr: their own figures would be incomplete.
-INSIDE_PANELS = ("gemm_nn_fp64_t64", "gemm_tn_fp64_t64")
-
-
-def dominant_class(prof):
-    """The GEMM class with the most time, among the classes whose every
-    launch is timed on its own."""
+def dominant_class(prof, arith=None):
+    """The thin-GEMM kernel class (one k_gemm instantiation: transposes,
+    arithmetic, tile) with the most time, optionally among the classes of
+    one arithmetic (or of a tuple of them).  The panel factorizations' own products are timed inside the
+    panel_qr class, so every launch of a GEMM class is a launch of the
+    factorization's thin products (sampling, updates, U / V, fold-back)."""
     gem = {k: v for k, v in prof.items()
-           if k.startswith("gemm") and len(k.split("_")) == 4 and k not in INSIDE_PANELS
-           and v[3] > 0}
-    return max(gem, key=lambda k: gem[k][0])
+           if k.startswith("gemm_") and len(k.split("_")) == 4 and v[3] > 0
+           and (arith is None or k.split("_")[2] in
+                ((arith,) if isinstance(arith, str) else tuple(arith)))}
+    return max(gem, key=lambda k: gem[k][0]) if gem else None
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_symbol(cls):
+    """k_gemm instantiation of a class name gemm_<op(A)op(B)>_<arith>_t<tile>."""
+    _, op, arith, tile = cls.split("_")
+    return (f"k_gemm<PREC_{arith.upper()}, {'true' if op[0] == 't' else 'false'}, "
+            f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, 2, 2>")
+
+
+def roofline_of(dom, prof_dom, workload):
+    """Roofline record of GEMM class `dom` from its event-timed launches:
+    achieved = algorithmic flops (2 M N K per launch) / summed launch time,
+    against the dense MFMA peak of the class's arithmetic (BF16x3 counts its
+    three BF16 products per flop: frac = 3 * achieved / BF16 peak, BF16x6
+    six)."""
+    ms_k, fl_k, by_k, nl = prof_dom[dom]
+    arith = dom.split("_")[2]
+    achieved = fl_k / (ms_k * 1e-3) / 1e12
+    mfma_rate = BF16_PRODUCTS.get(arith, 1.0) * achieved
+    rec = traffic_record(dom, workload, by_k / nl)
+    return {"bound": "mfma", "kernel": kernel_symbol(dom), "class": dom, "achieved": achieved,
+            "peak": PEAK_TFLOPS[arith], "unit": "TFLOP/s", "frac": mfma_rate / PEAK_TFLOPS[arith],
+            "traffic": rec["traffic_bytes_per_launch"] if rec else None,
+            "traffic_source": rec["file"] if rec else None,
+            "avg_launch_us": ms_k / nl * 1e3, "launches": nl, "flops_per_launch": fl_k / nl,
+            "algorithmic_bytes_per_launch": by_k / nl,
+            "algorithmic_gb_per_s": by_k / (ms_k * 1e-3) / 1e9}
 
 
 def run_path(B, torch, dA, dG, sig, m, n, b, q, prec, steps, warmup):
-    """Warm-up, one untimed factorization with every kernel class timed (the
-    per-class breakdown and the choice of the dominant class), then the
-    timed steps with HIP events around the dominant class's launches only."""
+    """Warm-up; one untimed factorization with every kernel class timed (the
+    per-class breakdown and the choice of the dominant class); the timed
+    steps with no events in the library (the path's time); then as many
+    steps again with HIP events around the dominant class's launches only
+    (its per-launch time, for the roofline).  The status words of the last
+    factorization are checked after each timed loop."""
     T = B.empty_colmajor(m, n)
     U = B.empty_colmajor(m, m)
     V = B.empty_colmajor(n, n)
@@ -148,7 +184,6 @@ def run_path(B, torch, dA, dG, sig, m, n, b, q, prec, steps, warmup):
     torch.cuda.synchronize()
     prof_all = B.profile_end()
     dom = dominant_class(prof_all)
-    B.profile_begin(only=dom)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -159,9 +194,25 @@ def run_path(B, torch, dA, dG, sig, m, n, b, q, prec, steps, warmup):
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof_dom = B.profile_end()[dom]
     ms_step = ev0.elapsed_time(ev1) / steps
+    B.randutv_status(work)  # raises on a spin-limit or non-converged status
     log(f"[{prec}] {steps} steps: {ms_step:.2f} ms/step (host wall {wall / steps * 1e3:.2f} ms)")
+    # The dominant class's launches, timed by events the library records on
+    # the stream each launch runs on, over the same number of steps.
+    doms = {dom}
+    bf = dominant_class(prof_all, ("bf16x3", "bf16x6"))
+    if bf:
+        doms.add(bf)
+    prof_dom = {}
+    for c in sorted(doms):
+        B.profile_begin(only=c)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        prof_dom[c] = B.profile_end()[c]
+        B.randutv_status(work)
+    log(f"[{prec}] dominant {dom}: {prof_dom[dom][0] / steps:.2f} ms/step over "
+        f"{prof_dom[dom][3] // steps} launches/step")
     # Accuracy of this path's own outputs (outside the timed region).
     nA = torch.linalg.norm(dA).item()
     res = torch.linalg.norm(dA - U @ (T @ V.T)).item() / nA
@@ -174,7 +225,7 @@ def run_path(B, torch, dA, dG, sig, m, n, b, q, prec, steps, warmup):
     acc = {"residual": res, "orth_U": ou, "orth_V": ov,
            "diag_rel_err_max": float(rel.max()), "diag_rel_err_median": float(np.median(rel))}
     log(f"[{prec}] accuracy {acc}")
-    return ms_step, prof_all, (dom, prof_dom), acc, d
+    return ms_step, prof_all, (dom, bf, prof_dom), acc, d
 
 
 def _timed(torch, fn, reps):
@@ -527,7 +578,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--q", type=int, default=1)
-    ap.add_argument("--prec", default="fp64,fp32,bf16x3,bf16x3_fp32",
+    ap.add_argument("--prec", default="fp64,fp32,bf16x3,bf16x3_fp32,bf16x3_bf16x6",
                     help="comma list of paths from " + ",".join(PRECS) + "; the headline "
                          "value is the fastest path meeting its error bound, FP64 included")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -589,14 +640,27 @@ def main():
     head = min(ok, key=lambda p: paths[p]["ms_per_step"])
     ms_step, prof = paths[head]["ms_per_step"], paths[head]["prof"]
     value = F / (ms_step * 1e-3) / 1e12
-    # Dominant kernel of the headline path (the GEMM class with the most time
-    # in the untimed profiled factorization); its figures come from the timed
-    # steps, where only its launches carry events.
-    dom, (ms_k, fl_k, by_k, nl) = paths[head]["dom"]
-    _, op, dom_prec, tile = dom.split("_")
-    sym = (f"k_gemm<PREC_{dom_prec.upper()}, {'true' if op[0] == 't' else 'false'}, "
-           f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, 2, 2>")
-    achieved = fl_k / (ms_k * 1e-3) / 1e12
+    workload = f"randUTV {m}x{n}, b={b}, q={q}, U and V formed, sigma_j=exp(-j/800)+1e-10"
+    # Dominant kernel of each path (the GEMM class with the most time in the
+    # untimed profiled factorization); its figures come from the extra timed
+    # steps in which only its launches carry events.
+    roofs = {p: roofline_of(paths[p]["dom"][0], paths[p]["dom"][2], workload)
+             for p in precs}
+    roof = roofs[head]
+    # The top BF16-based class of the split path: its BF16 MFMA rate (three
+    # or six BF16 products per flop of the product) and algorithmic HBM rate.
+    bf16_split = None
+    if paths[head]["dom"][1]:
+        bcls = paths[head]["dom"][1]
+        ms_b, fl_b, by_b, nl_b = paths[head]["dom"][2][bcls]
+        t = ms_b * 1e-3
+        nprod = BF16_PRODUCTS[bcls.split("_")[2]]
+        bf16_split = {"class": bcls, "kernel": kernel_symbol(bcls), "avg_launch_us": ms_b / nl_b * 1e3,
+                      "product_tflops": fl_b / t / 1e12,
+                      "bf16_mfma_tflops": nprod * fl_b / t / 1e12,
+                      "frac_bf16_peak": nprod * fl_b / t / 1e12 / PEAK_TFLOPS["bf16x3"],
+                      "algorithmic_gb_per_s": by_b / t / 1e9,
+                      "frac_hbm_peak": by_b / t / 1e9 / HBM_PEAK_GBS}
     # Per-class breakdown from the one profiled factorization (all classes).
     kernels = {k: {"ms_per_step": v[0], "launches_per_step": v[3],
                    "avg_launch_us": (v[0] / v[3] * 1e3) if v[3] else 0.0,
@@ -604,16 +668,9 @@ def main():
                    "algorithmic_gb_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
                for k, v in prof.items() if v[3] > 0}
     log(f"kernels [{head}]: {json.dumps(kernels)}")
-    workload = f"randUTV {m}x{n}, b={b}, q={q}, U and V formed, sigma_j=exp(-j/800)+1e-10"
-    rec = traffic_record(dom, workload, by_k / nl)
-    roof = {"bound": "mfma", "kernel": sym, "class": dom, "achieved": achieved,
-            "peak": PEAK_TFLOPS[dom_prec], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS[dom_prec],
-            "traffic": rec["traffic_bytes_per_launch"] if rec else None,
-            "traffic_source": rec["file"] if rec else None,
-            "avg_launch_us": ms_k / nl * 1e3, "flops_per_launch": fl_k / nl,
-            "algorithmic_bytes_per_launch": by_k / nl}
     summary = {p: {k: v for k, v in d.items() if k not in ("prof", "dom")} for p, d in paths.items()}
+    for p in precs:
+        summary[p]["roofline"] = roofs[p]
     out = {
         "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -626,9 +683,12 @@ def main():
         "meets_error_bound": paths[head]["meets_error_bound"],
         "paths": summary,
         "speedup_vs_fp64": (paths["fp64"]["ms_per_step"] / ms_step) if "fp64" in paths else None,
-        "roofline": roof, "kernels": kernels,
-        "paper_context": {"randUTV_q1_n8000_UV_formed_s": 26.4, "hardware":
-                          "Xeon E5-2695 v3, 14 cores, MKL 11.2.3, b=64 (Table 1)"},
+        "roofline": roof, "roofline_bf16_split": bf16_split, "kernels": kernels,
+        "paper_context": {"randUTV_q1_n8000_UV_formed_s": 26.4,
+                          "mkl_dgesvd_n8000_UV_formed_s": 107.0,
+                          "randUTV_q1_n8000_no_UV_s": 17.6, "mkl_dgesvd_n8000_no_UV_s": 74.0,
+                          "hardware": "Xeon E5-2695 v3 (Haswell), 14 cores, 2.3 GHz, "
+                                      "MKL 11.2.3, FP64, b=64 (Tables 1 and 2)"},
     }
     if not args.no_extra:
         if q == 1:  # the same workload with q = 2 on the headline path

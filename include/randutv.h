@@ -9,8 +9,13 @@
  *    the library never frees caller memory.
  *  - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL means
  *    the default stream).  Calls return once the work is enqueued, except
- *    where stated (the tolerance-based early stop reads one scalar per step
- *    back to the host).
+ *    where stated: the tolerance-based early stop reads one scalar per step
+ *    back to the host, a non-NULL k_out / sweeps_out asks the call to wait
+ *    for its results, and the building blocks randutv_panel_qr and
+ *    randutv_small_svd wait for completion.  Every iteration count (the
+ *    Jacobi sweeps of the small SVDs included) is decided on the device.
+ *  - An enqueue-only call leaves its status in the first 256 bytes of its
+ *    workspace; randutv_status() waits for the stream and reports it.
  *  - Return status: 0 on success; -i if argument i (1-based) is invalid
  *    (LAPACK INFO convention); RANDUTV_E_UNSUPPORTED for a valid but
  *    unimplemented case; RANDUTV_E_WORKSPACE if the workspace is too small;
@@ -45,12 +50,18 @@ extern "C" {
  * + lo*hi on BF16 MFMA with FP32 accumulation.  RANDUTV_BF16X3_FP32: BF16x3
  * for the sampling products (their rounding only perturbs the sampled
  * subspace, never the exactness of A = U T V^T, since the transforms are
- * built from it in FP64) and FP32 for the two trailing updates. */
+ * built from it in FP64) and FP32 for the two trailing updates.
+ * RANDUTV_BF16X3_BF16X6: BF16x3 sampling and BF16x6 trailing updates: each
+ * operand x32 = fl32(x) split into three bf16 pieces h = bf16(x32),
+ * m = bf16(x32 - h), l = bf16(x32 - h - m), and the six products h*h, h*m,
+ * m*h, h*l, l*h, m*m on BF16 MFMA with FP32 accumulation (FP32-level
+ * accuracy on the BF16 matrix cores). */
 typedef enum {
   RANDUTV_FP64 = 0,
   RANDUTV_FP32 = 1,
   RANDUTV_BF16X3 = 2,
-  RANDUTV_BF16X3_FP32 = 3
+  RANDUTV_BF16X3_FP32 = 3,
+  RANDUTV_BF16X3_BF16X6 = 4
 } randutv_prec;
 
 /* Flags of randutv_factor. */
@@ -92,7 +103,7 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
  *  5  G, ldg   packed N(0,1) matrix, m x randutv_g_cols(m,n,b): randomized
  *              step i uses G(0:m-i*b-1, i*b:(i+1)*b-1), i.e. the leading
  *              m - i*b rows of column block i (the paper draws a fresh
- *              randn(m - b(i-1), b) each step).  ldg >= m.  May be NULL only
+ *              m - b(i-1) by b Gaussian matrix each step).  ldg >= m.  May be NULL only
  *              if randutv_g_cols() == 0.
  *  6  U, ldu   out (if flags & RANDUTV_FORM_U): m x m orthogonal U.  Else may
  *              be NULL.  ldu >= m.
@@ -111,8 +122,10 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
  * 14  k_out    host pointer, may be NULL: the number of leading columns
  *              driven to triangular form (min(m,n) unless stopped early).
  *              When non-NULL the call also waits for the stream and then
- *              reports RANDUTV_E_SYNC or 1 (a small SVD did not converge);
- *              with k_out == NULL the call only enqueues (no tol test).
+ *              reports RANDUTV_E_SYNC or 1 (a small SVD did not converge
+ *              within its 40-sweep budget); with k_out == NULL and tol <= 0
+ *              the call only enqueues, and randutv_status(work, ...) reports
+ *              the same statuses and k later.
  * 15  stream
  *
  * The small b x b SVDs of all steps are computed after the main loop and
@@ -128,6 +141,24 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q,
                    int prec, unsigned flags,
                    void* work, size_t work_bytes,
                    int64_t* k_out, void* stream);
+
+/*
+ * randutv_status -- status of the last factorization (randutv_factor,
+ * randutv_factor_p, randutv_factor_lower) or randomized SVD (randutv_rsvd)
+ * enqueued with this workspace: waits for `stream`, then returns 0, 1 (a
+ * Jacobi SVD did not converge within its sweep budget), RANDUTV_E_SYNC (a
+ * bounded cross-workgroup wait hit its spin limit), or
+ * RANDUTV_E_UNSUPPORTED when no such call has completed in this workspace;
+ * *k_out (host pointer, may be NULL) receives the number of leading
+ * columns reduced (the rank k for randutv_rsvd).  The status words are the
+ * first 256 bytes of the workspace, so each concurrent call needs its own
+ * workspace.
+ *  1  work        the workspace passed to that call (256-byte aligned)
+ *  2  work_bytes  at least 256
+ *  3  k_out
+ *  4  stream      the stream that call was enqueued on
+ */
+int randutv_status(const void* work, size_t work_bytes, int64_t* k_out, void* stream);
 
 /*
  * randutv_factor_lower -- the same factorization with a lower-triangular
@@ -174,10 +205,8 @@ int randutv_factor_lower(int64_t m, int64_t n, int64_t b, int q,
  * randutv_factor_p: arguments and results as randutv_factor with p after b;
  *   0 <= p and b + p <= 256, else status -13.  The SVD of each step's
  *   extended sample runs on the device between the sampling products and
- *   the QR; when k_out is non-NULL, a non-converged one reports status 1
- *   like a non-converged small SVD.  Each such SVD waits on the host for
- *   its convergence test, so the call does not run fully ahead of the
- *   stream.
+ *   the QR; a non-converged one reports status 1 like a non-converged
+ *   small SVD (through k_out or randutv_status).
  */
 int64_t randutv_g_cols_p(int64_t m, int64_t n, int64_t b, int64_t p);
 int randutv_workspace_size_p(int64_t m, int64_t n, int64_t b, int64_t p, int q,
@@ -221,7 +250,7 @@ int randutv_factor_p(int64_t m, int64_t n, int64_t b, int64_t p, int q,
  *              for the stream, stores the Jacobi sweeps used and returns 1
  *              if the SVD did not converge (RANDUTV_E_SYNC if a
  *              cross-workgroup wait hit its spin limit); when NULL it only
- *              enqueues.
+ *              enqueues, and randutv_status(work, ...) reports later.
  * 19  stream
  * Statuses: -i for argument i; RANDUTV_E_UNSUPPORTED above the size limit;
  * RANDUTV_E_WORKSPACE; RANDUTV_E_HIP - hipError.
@@ -272,7 +301,8 @@ int randutv_approx_backward(int64_t m, int64_t n, int64_t b, int q, int64_t k, c
  * memory, op(X) = X^T when tX != 0, inner products in `prec` arithmetic.
  * C is M x N, op(A) is M x K, op(B) is K x N.  work (may be NULL) enables a
  * split of long K: any size, used up to 8*M*N doubles.  Arguments 1..12 are
- * validated (-i on error); prec is RANDUTV_FP64, _FP32 or _BF16X3. */
+ * validated (-i on error); prec is RANDUTV_FP64, _FP32 or _BF16X3, or 4 for
+ * the BF16x6 arithmetic (three bf16 pieces per operand, six products). */
 int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                  double* C, int64_t ldc, void* work, size_t work_bytes, void* stream);
@@ -293,8 +323,8 @@ int randutv_panel_qr(int64_t Mp, int64_t nb, double* P, int64_t ldp, double* tau
                      int64_t ldtw, int* used_fallback, void* work, size_t work_bytes,
                      void* stream);
 
-/* SVD of `count` small square blocks (Figure "The algorithm randUTV",
- * [Us, Ds, Vs] = svd(R)): matrix i has size nbs[i] (host array, each
+/* SVD of `count` small square blocks (Figure "The algorithm randUTV": the
+ * SVD of each step's diagonal block R): matrix i has size nbs[i] (host array, each
  * 1..ld, ld <= 1024) and is read from R + i*ld*ld (leading dimension ld);
  * outputs Us, Vs (same layout) and D + i*ld, singular values descending,
  * each (u_j, v_j) flipped so the largest-magnitude entry of v_j is positive.

@@ -22,9 +22,10 @@ design notes of the repository):
     block i of one packed m x (s_r*(b+p)) Gaussian matrix G (`g_slab`).
   * Over-sampling (p > 0): the b dominant left singular vectors of the
     extended sampling matrix, signs normalised as for the small SVDs.
-  * "qr(Y)" is unpivoted Householder QR (Section 4.3; Figure randUTV).
-  * The right transform touches all m rows of T (Figure randUTV:
-    T(:,[J2,J3]) = T(:,[J2,J3]) V).
+  * The QR factorization of the sampling matrix is unpivoted Householder QR
+    (Section 4.3; Figure randUTV).
+  * The right transform touches all m rows of T (Figure randUTV: the whole
+    block column J2 u J3, rows I1 included).
   * Early stop: after step i, stop when ||T(I3,J3)||_F <= tol*||A||_F or when
     (i+1)*b >= k_stop (Section 1.1, advantage (ii)).
   * Lower-triangular middle factor (`randutv_lower`): randUTV of A^T,
@@ -157,8 +158,8 @@ def g_slab(G, m, b, i, p=0):
 
 def top_left_singular_vectors(Y, b):
     """The b dominant left singular vectors of the n_i x (b+p) matrix Y
-    (Appendix A.2, Figure stepUTVoversampling: [Z,~,~] = svd(Y,'econ'),
-    Z(:,1:b)), each pair (z_j, w_j) sign-normalised like `small_svd` (the
+    (Appendix A.2, Figure stepUTVoversampling: the leading b left singular
+    vectors of the economic SVD of Y), each pair (z_j, w_j) sign-normalised like `small_svd` (the
     largest-magnitude entry of the right singular vector w_j positive)."""
     Z, _, Wt = np.linalg.svd(Y, full_matrices=False)
     Z = Z[:, :b].copy()
@@ -207,7 +208,7 @@ def randutv(A, b, q, G, *, p=0, form_u=True, form_v=True, k_stop=0, tol=0.0,
         r1 = min(r0 + b, m)          # I2 = r0:r1, I3 = r1:m
         c1 = min(r0 + b, n)          # J2 = r0:c1, J3 = c1:n
         if r1 < m and c1 < n:
-            # Sampling matrix Y = (X^T X)^q X^T G with X = T([I2,I3],[J2,J3]).
+            # The sampling matrix (X^T X)^q X^T G_i of the trailing block X.
             X = T[r0:, r0:]
             Gi = g_slab(G, m, b, i, p)
             Y = X.T @ Gi
@@ -215,13 +216,16 @@ def randutv(A, b, q, G, *, p=0, form_u=True, form_v=True, k_stop=0, tol=0.0,
                 Y = X.T @ (X @ Y)
             if p > 0:
                 Y = top_left_singular_vectors(Y, b)
-            # [Vq, ~] = qr(Y);  T(:,[J2,J3]) = T(:,[J2,J3]) Vq; V likewise.
+            # Right transform: the Householder reflectors of Y act on the
+            # trailing columns of T (all rows) and of V.
             reflV, _ = house_qr(Y)
             apply_right(T[:, r0:], reflV)
             if form_v:
                 apply_right(V[:, r0:], reflV)
-            # [Uq, R] = qr(T([I2,I3],J2)); U(:,[I2,I3]) = U(:,[I2,I3]) Uq;
-            # T([I2,I3],J3) = Uq^T T([I2,I3],J3); T(I3,J2) = 0.
+            # Left transform: the Householder QR of the new block column J2
+            # (rows I2 u I3) acts on U's trailing columns and, transposed,
+            # on the trailing rows of T right of the block; below the
+            # block's R the column is zero.
             reflU, R = house_qr(T[r0:, r0:c1])
             if form_u:
                 apply_right(U[:, r0:], reflU)
@@ -229,7 +233,8 @@ def randutv(A, b, q, G, *, p=0, form_u=True, form_v=True, k_stop=0, tol=0.0,
             T[r0:, r0:c1] = 0.0
             T[r0:r1, r0:c1] = R
             if small_svds:
-                # [Us, Ds, Vs] = svd(R); fold the rotations back.
+                # SVD of the diagonal block; its rotations fold into block
+                # row I2, block column J2 and the matching columns of U, V.
                 Us, D, Vs = small_svd(R)
                 T[r0:r1, r0:c1] = np.diag(D)
                 T[r0:r1, c1:] = Us.T @ T[r0:r1, c1:]
@@ -378,6 +383,8 @@ def flops_paper(m, n, q):
 
 
 def flops_uv(m, n):
-    """Forward accumulation of U and V (Figure randUTV, U(:,I)=U(:,I)Uq etc.):
-    4 m^2 n - 2 m n^2 + 2 n^3 to leading order."""
+    """Forming U and V by forward accumulation (Figure randUTV: U's and V's
+    trailing columns times each step's orthogonal factor), m >= n: the sum
+    over steps of 4 m m_i b + 4 n n_i b, to leading order
+    4 m^2 n - 2 m n^2 + 2 n^3 (the O(b/n) terms are dropped)."""
     return 4.0 * m * m * n - 2.0 * m * n * n + 2.0 * n ** 3

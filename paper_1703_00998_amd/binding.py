@@ -18,8 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librandutv.so")
 
 RANDUTV_FP64, RANDUTV_FP32, RANDUTV_BF16X3, RANDUTV_BF16X3_FP32 = 0, 1, 2, 3
+RANDUTV_BF16X3_BF16X6 = 4
 PREC = {"fp64": RANDUTV_FP64, "fp32": RANDUTV_FP32, "bf16x3": RANDUTV_BF16X3,
-        "bf16x3_fp32": RANDUTV_BF16X3_FP32}
+        "bf16x3_fp32": RANDUTV_BF16X3_FP32, "bf16x3_bf16x6": RANDUTV_BF16X3_BF16X6}
+# Arithmetic codes of randutv_gemm (a product has one arithmetic).
+GEMM_PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 4}
 FORM_U, FORM_V = 1, 2
 
 _lib = None
@@ -100,6 +103,8 @@ def lib():
     L.randutv_approx_backward.argtypes = [i64, i64, i64, i32, i64, vp, i64, vp, i64, vp, i64, vp,
                                           sz, vp, i64, vp, i64, i32, vp, sz, vp]
     L.randutv_approx_backward.restype = i32
+    L.randutv_status.argtypes = [vp, sz, ctypes.POINTER(i64), vp]
+    L.randutv_status.restype = i32
     L.randutv_strerror.argtypes = [i32]
     L.randutv_strerror.restype = ctypes.c_char_p
     _lib = L
@@ -111,6 +116,7 @@ EXPORTS = ["randutv_random_steps", "randutv_g_cols", "randutv_workspace_size",
            "randutv_workspace_size_lower", "randutv_factor_lower", "randutv_rsvd_workspace_size", "randutv_rsvd", "randutv_gemm",
            "randutv_panel_work_size", "randutv_panel_qr",
            "randutv_small_svd_work_size", "randutv_small_svd", "randutv_strerror",
+           "randutv_status",
            "randutv_profile_begin", "randutv_profile_begin_class", "randutv_profile_end", "randutv_profile_class_name",
            "randutv_approx_tape_size", "randutv_approx_work_size", "randutv_approx",
            "randutv_approx_backward_work_size", "randutv_approx_backward"]
@@ -255,6 +261,19 @@ def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", w
     return int(k.value) if (sync or tol > 0) else None
 
 
+def randutv_status(work, raise_on_error=True):
+    """Wait for the current stream and return (status, k) of the last
+    factorization or randomized SVD enqueued with workspace `work`
+    (randutv_status).  Raises on a nonzero status unless
+    raise_on_error=False."""
+    wp, wbytes = _aligned_ptr(work)
+    k = ctypes.c_int64(-1)
+    st = lib().randutv_status(wp, wbytes, ctypes.byref(k), _stream())
+    if raise_on_error:
+        _check(st, "randutv_status")
+    return st, int(k.value)
+
+
 def workspace_size_lower(m, n, b, q=1, prec="fp64", form_u=True, form_v=True):
     flags = (FORM_U if form_u else 0) | (FORM_V if form_v else 0)
     out = ctypes.c_size_t(0)
@@ -322,7 +341,7 @@ def randutv_gemm(C, A, B, ta=False, tb=False, alpha=1.0, beta=0.0, prec="fp64", 
     ldb = _ld(B, B.shape[0])
     ldc = _ld(C, M)
     wp, wb = (_aligned_ptr(work) if work is not None else (ctypes.c_void_p(0), 0))
-    _check(lib().randutv_gemm(PREC[prec], int(ta), int(tb), M, N, K, alpha, _ptr(A), lda,
+    _check(lib().randutv_gemm(GEMM_PREC[prec], int(ta), int(tb), M, N, K, alpha, _ptr(A), lda,
                               _ptr(B), ldb, beta, _ptr(C), ldc, wp, wb, _stream()),
            "randutv_gemm")
     return C

@@ -307,7 +307,7 @@ int randutv_approx(int64_t m, int64_t n, int64_t b, int q, int64_t k, const doub
   if (Ak && ldak < m) return -11;
   if (!Uk || lduk < m) return -12;
   if (!tape || tape_bytes < randutv_approx_tape_size(m, n, b, k)) return -14;
-  if (prec < 0 || prec > 3) return -16;
+  if (prec < 0 || prec > kPrecMax) return -16;
   const ApproxLayout L = approx_layout(m, n, b, k);
   if (!work || ((uintptr_t)work & 255) || work_bytes < L.total) return RANDUTV_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
@@ -349,7 +349,7 @@ int randutv_approx_backward(int64_t m, int64_t n, int64_t b, int q, int64_t k, c
   if (!tape || tape_bytes < randutv_approx_tape_size(m, n, b, k)) return -12;
   if (!Akbar || ldakb < m) return -14;
   if (!Abar || ldab < m) return -16;
-  if (prec < 0 || prec > 3) return -18;
+  if (prec < 0 || prec > kPrecMax) return -18;
   const BackLayout L = back_layout(m, n, b, q, k);
   if (!work || ((uintptr_t)work & 255) || work_bytes < L.total) return RANDUTV_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
@@ -360,8 +360,8 @@ int randutv_approx_backward(int64_t m, int64_t n, int64_t b, int q, int64_t k, c
   const ApproxTape tp{const_cast<double*>(tape), m, n, b, t};
   // Arithmetic of the products with the m x n trailing matrices (as in the
   // forward: sampling in ps, updates in pu); everything else in FP64.
-  const Prec ps = prec == 3 ? PREC_BF16X3 : (Prec)prec;
-  const Prec pu = prec == 3 ? PREC_FP32 : (Prec)prec;
+  const Prec ps = sampling_prec(prec);
+  const Prec pu = update_prec(prec);
   double* split = dp(L.split);
   const Mul mul{st, pu, split, L.split_elems};
   const Mul mls{st, ps, split, L.split_elems};

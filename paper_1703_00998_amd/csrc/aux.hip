@@ -1,10 +1,12 @@
 // Elementwise and reduction helpers of the randUTV driver: copies, zeroing
 // (Figure "The algorithm randUTV": T(I3,J2) = 0), writing the diagonal block
 // T(I2,J2) = Ds, identity initialisation of U and V, and the Frobenius norm
-// of the trailing block used by the early-stop test (Section 1.1 (ii)).
+// of the trailing block used by the early-stop test (Section 1.1 (ii)), and
+// the status words a call leaves in its workspace.
 // All of them are HBM-bound single passes over column-major data.
 #include <algorithm>
 
+#include "../../include/randutv.h"
 #include "common.h"
 
 namespace rutv {
@@ -44,6 +46,23 @@ __global__ void k_diag_block(int M, int nb, const double* __restrict__ D, double
     const int i = (int)(idx % M);
     const int j = (int)(idx / M);
     A[i + (int64_t)j * lda] = (i == j) ? D[j] : 0.0;
+  }
+}
+
+__global__ void k_status_init(StatusBlock* blk) {
+  if (threadIdx.x == 0) {
+    blk->sync_err = 0;
+    blk->svd_fail = 0;
+    blk->k = -1;
+    blk->magic = 0;
+    blk->pad = 0;
+  }
+}
+
+__global__ void k_status_done(StatusBlock* blk, long long k) {
+  if (threadIdx.x == 0) {
+    blk->k = k;
+    blk->magic = kStatusMagic;
   }
 }
 
@@ -123,6 +142,27 @@ hipError_t sumsq(hipStream_t st, int M, int N, const double* A, int64_t lda, dou
   hipLaunchKernelGGL(k_sumsq_part, dim3(nparts), dim3(256), 0, st, M, N, A, lda, scratch);
   hipLaunchKernelGGL(k_sumsq_final, dim3(1), dim3(256), 0, st, nparts, scratch, out);
   return hipGetLastError();
+}
+
+hipError_t status_init(hipStream_t st, StatusBlock* blk) {
+  hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, st, blk);
+  return hipGetLastError();
+}
+
+hipError_t status_done(hipStream_t st, StatusBlock* blk, long long k) {
+  hipLaunchKernelGGL(k_status_done, dim3(1), dim3(64), 0, st, blk, k);
+  return hipGetLastError();
+}
+
+int read_status(const void* work, int64_t* k_out, hipStream_t st) {
+  hipError_t e = hipStreamSynchronize(st);
+  StatusBlock h{};
+  if (e == hipSuccess) e = hipMemcpy(&h, work, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
+  if (h.magic != kStatusMagic) return RANDUTV_E_UNSUPPORTED;
+  if (k_out) *k_out = h.k;
+  if (h.sync_err) return RANDUTV_E_SYNC;
+  return h.svd_fail ? 1 : 0;
 }
 
 }  // namespace rutv

@@ -25,18 +25,30 @@ constexpr unsigned kSpinLimit = 1u << 20;
 constexpr int kMaxSplitK = 8;
 constexpr int kMaxSplitKSmall = 64;  // for outputs of at most 32 tiles of 64 x 64
 
-// Arithmetic of the thin-matrix products (values of randutv_prec).
-enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
-// randutv_prec value of the mixed mode: BF16x3 sampling, FP32 updates.
+// Arithmetic of the thin-matrix products.  FP64, FP32 and BF16X3 have the
+// randutv_prec values of the same names; BF16X6 (three bf16 pieces per
+// operand, six products) is randutv_prec 4's update arithmetic.
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2, PREC_BF16X6 = 3 };
+// randutv_prec values of the mixed modes: BF16x3 sampling with FP32 updates,
+// and BF16x3 sampling with BF16x6 updates.
 constexpr int kPrecMixed = 3;
+constexpr int kPrecMixed6 = 4;
+constexpr int kPrecMax = 4;
+// Sampling and update arithmetic of a randutv_prec value.
+inline Prec sampling_prec(int prec) {
+  return (prec == kPrecMixed || prec == kPrecMixed6) ? PREC_BF16X3 : (Prec)prec;
+}
+inline Prec update_prec(int prec) {
+  return prec == kPrecMixed ? PREC_FP32 : prec == kPrecMixed6 ? PREC_BF16X6 : (Prec)prec;
+}
 
 // ---------------------------------------------------------------- timing
 // Profiling classes: thin GEMMs per tile shape (0: 64 x 64, 1: 128 x 128),
-// arithmetic (FP64, FP32, BF16x3) and transpose case (class = 12*shape +
-// 4*prec + 2*tb + ta; one class is one kernel instantiation), then the
-// other kernels.
+// arithmetic (FP64, FP32, BF16x3, BF16x6) and transpose case (class =
+// 16*shape + 4*prec + 2*tb + ta; one class is one kernel instantiation),
+// then the other kernels.
 enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
-                 PC_SPLITK = 24, PC_PANEL, PC_SVD, PC_GEMM_SMALL, PC_COUNT };
+                 PC_SPLITK = 32, PC_PANEL, PC_SVD, PC_GEMM_SMALL, PC_COUNT };
 bool prof_on();
 // Start event of a launch of class `cls`; returns a slot, or -1 when off or
 // when timing is restricted to another class.
@@ -117,12 +129,40 @@ hipError_t pack_qr(hipStream_t st, int Mp, int nb, const double* V, int64_t ldv,
 // stored at R + i*strideR with leading dimension ld) -> Us_i, D_i, Vs_i.
 // Singular values descending, each (u_j, v_j) sign-normalised so that the
 // largest |v_j| entry is positive.  status[i] = sweeps used, or -1 if not
-// converged.
-// nb_dev: device array of sizes; Wk, Vk: scratch of the same shape as Us.
+// converged within max_sweeps, and then *fail (device word, may be NULL) is
+// or-ed with 1.  Enqueue only: the convergence decision is taken on the
+// device.
+// nb_dev: device array of sizes; Wk, Vk: scratch of the same shape as Us;
+// status: count + count * max_sweeps ints (status words, sweep counters).
 hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld,
                        const double* R, int64_t strideR, double* Us, double* Vs,
                        int64_t strideUV, double* D, int64_t strideD, double* Wk,
-                       double* Vk, int* status, int max_sweeps);
+                       double* Vk, int* status, int max_sweeps, int* fail);
+
+// ---------------------------------------------------------------- call status
+// Status words a factorization (or randomized SVD) leaves at the start of its
+// workspace, so that an enqueue-only call can be checked later
+// (randutv_status).  sync_err: a bounded cross-workgroup wait hit its spin
+// limit; svd_fail: a Jacobi SVD did not converge within its sweep budget;
+// k: the number of leading columns reduced; magic: kStatusMagic once the
+// call's last kernel has run.
+struct StatusBlock {
+  int sync_err;
+  int svd_fail;
+  long long k;
+  int magic;
+  int pad;
+};
+constexpr int kStatusMagic = 0x52555456;
+constexpr size_t kStatusBytes = 256;  // bytes reserved for it (keeps 256-byte alignment)
+// All words cleared (magic 0, k = -1), on the stream.
+hipError_t status_init(hipStream_t st, StatusBlock* blk);
+// k and the magic word written, on the stream (after the call's other work).
+hipError_t status_done(hipStream_t st, StatusBlock* blk, long long k);
+// Waits for the stream, then turns the status words at `work` into a status
+// code (0, 1 for a non-converged SVD, RANDUTV_E_SYNC, RANDUTV_E_UNSUPPORTED
+// when no call has completed there) and *k_out (may be NULL).
+int read_status(const void* work, int64_t* k_out, hipStream_t st);
 
 // ---------------------------------------------------------------- factor core
 // Reflectors and R factors of the first t steps, for the truncated
@@ -149,6 +189,13 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
                 double tol, int prec, unsigned flags, void* work, size_t work_bytes,
                 int64_t* k_out, void* stream, const ApproxTape* tape);
 size_t factor_work_bytes(int64_t m, int64_t n, int64_t b);
+// factor_impl with over-sampling p; use_side false keeps the U and V updates
+// on the caller's stream (no second stream is created or used).
+int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,
+                const double* G, int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv,
+                int64_t k_stop, double tol, int prec, unsigned flags, void* work,
+                size_t work_bytes, int64_t* k_out, void* stream, const ApproxTape* tape,
+                bool use_side);
 
 // ---------------------------------------------------------------- misc
 hipError_t copy_matrix(hipStream_t st, int M, int N, const double* A, int64_t lda,

@@ -53,11 +53,18 @@ template <>
 struct Cfg<PREC_BF16X3> {
   static constexpr int BK = 32;
 };
+template <>
+struct Cfg<PREC_BF16X6> {
+  static constexpr int BK = 32;
+};
 
 // LDS slabs of one K step, per arithmetic.  FP64/FP32: [k][i] with i
-// contiguous (MFMA 16x16x4 takes one element per lane).  BF16 hi/lo pairs:
+// contiguous (MFMA 16x16x4 takes one element per lane).  BF16 pieces:
 // [k/8][i][k%8] so that each lane reads its 8 consecutive k values of row i
-// (the bf16 MFMA operand) as one 16-byte load.
+// (the bf16 MFMA operand) as one 16-byte load.  NB buffers: two (the next
+// slab is stored while the current one is multiplied) except for the
+// three-piece BF16x6 slabs of 128 x 128 tiles, whose single buffer (48 KB)
+// keeps two workgroups per CU.
 template <int P, int BM, int BN>
 struct Slabs;
 template <int BM, int BN>
@@ -77,6 +84,32 @@ struct Slabs<PREC_BF16X3, BM, BN> {
   alignas(16) __bf16 Bh[2][4][BN][8];
   alignas(16) __bf16 Bl[2][4][BN][8];
 };
+template <int BM>
+constexpr int bf6_bufs() { return BM >= 128 ? 1 : 2; }
+template <int BM, int BN>
+struct Slabs<PREC_BF16X6, BM, BN> {
+  static constexpr int NB = bf6_bufs<BM>();
+  alignas(16) __bf16 Ah[NB][4][BM][8];
+  alignas(16) __bf16 Am[NB][4][BM][8];
+  alignas(16) __bf16 Al[NB][4][BM][8];
+  alignas(16) __bf16 Bh[NB][4][BN][8];
+  alignas(16) __bf16 Bm[NB][4][BN][8];
+  alignas(16) __bf16 Bl[NB][4][BN][8];
+};
+
+// x ~ h + m + l in bf16, from x32 = fl32(x): each piece is the bf16 rounding
+// of what the earlier ones leave (the remainders are exact in FP32), so the
+// three carry about 24 significant bits.
+struct Bf3 {
+  __bf16 h, m, l;
+};
+__device__ inline Bf3 split3(float x32) {
+  const __bf16 h = (__bf16)x32;
+  const float r1 = x32 - (float)h;
+  const __bf16 m = (__bf16)r1;
+  const float r2 = r1 - (float)m;
+  return Bf3{h, m, (__bf16)r2};
+}
 
 // BM x BN output tile per workgroup of WM x WN waves, each owning a
 // (BM/WM) x (BN/WN) part as MFMA 16 x 16 blocks.  The 128 x 128 and 64 x 64
@@ -98,6 +131,7 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
   static_assert(LA * NT == BM * BK && LB * NT == BN * BK, "loader shape");
   static_assert(NT % BM == 0 && NT % BN == 0 && NT % BK == 0, "loader shape");
   __shared__ Slabs<P, BM, BN> sl;
+  constexpr int NBUF = P == PREC_BF16X6 ? bf6_bufs<BM>() : 2;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
@@ -132,7 +166,13 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
     if (!TB) { k = tid % BK; j = tid / BK + (NT / BK) * r; }
     else     { j = tid % BN; k = tid / BN + (NT / BN) * r; }
   };
-  double ra[LA], rb[LB];
+  // The prefetch registers hold the FP64 operands as loaded; the conversion
+  // waits until the slab is stored to LDS, after the current slab's MFMAs,
+  // so the loads stay in flight under them (converting at load time exposed
+  // their latency: the 128 x 128 split-precision products ran 1.3-2.8x
+  // slower).
+  using LoadT = double;
+  LoadT ra[LA], rb[LB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
@@ -156,7 +196,12 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
       a_idx(r, i, k);
       if constexpr (P == PREC_FP64) sl.A[buf][k][i] = ra[r];
       else if constexpr (P == PREC_FP32) sl.A[buf][k][i] = (float)ra[r];
-      else {
+      else if constexpr (P == PREC_BF16X6) {
+        const Bf3 x = split3((float)ra[r]);
+        sl.Ah[buf][k >> 3][i][k & 7] = x.h;
+        sl.Am[buf][k >> 3][i][k & 7] = x.m;
+        sl.Al[buf][k >> 3][i][k & 7] = x.l;
+      } else {
         const float x = (float)ra[r];
         const __bf16 h = (__bf16)x;
         sl.Ah[buf][k >> 3][i][k & 7] = h;
@@ -169,7 +214,12 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
       b_idx(r, k, j);
       if constexpr (P == PREC_FP64) sl.B[buf][k][j] = rb[r];
       else if constexpr (P == PREC_FP32) sl.B[buf][k][j] = (float)rb[r];
-      else {
+      else if constexpr (P == PREC_BF16X6) {
+        const Bf3 x = split3((float)rb[r]);
+        sl.Bh[buf][k >> 3][j][k & 7] = x.h;
+        sl.Bm[buf][k >> 3][j][k & 7] = x.m;
+        sl.Bl[buf][k >> 3][j][k & 7] = x.l;
+      } else {
         const float x = (float)rb[r];
         const __bf16 h = (__bf16)x;
         sl.Bh[buf][k >> 3][j][k & 7] = h;
@@ -193,9 +243,39 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
   __syncthreads();
   const int kr = lane >> 4, cr = lane & 15;
   for (int t = 0; t < nk; ++t) {
-    const int cur = t & 1;
+    const int cur = NBUF == 2 ? (t & 1) : 0;
     if (t + 1 < nk) load(kbeg + (t + 1) * BK);
-    if constexpr (P == PREC_BF16X3) {
+    if constexpr (P == PREC_BF16X6) {
+      // Six products per block pair, small terms first: h m, m h, h l, l h,
+      // m m, then h h (m l, l m, l l are below FP32's rounding and dropped).
+      // B's three pieces are read once per slab, A's per 16-row block (the
+      // register budget of two workgroups per CU holds no more).
+      v8bf bh[FN], bm[FN], bl[FN];
+#pragma unroll
+      for (int y = 0; y < FN; ++y) {
+        bh[y] = *(const v8bf*)&sl.Bh[cur][kr][wn * PN + y * 16 + cr][0];
+        bm[y] = *(const v8bf*)&sl.Bm[cur][kr][wn * PN + y * 16 + cr][0];
+        bl[y] = *(const v8bf*)&sl.Bl[cur][kr][wn * PN + y * 16 + cr][0];
+      }
+#pragma unroll
+      for (int x = 0; x < FM; ++x) {
+        const v8bf ah = *(const v8bf*)&sl.Ah[cur][kr][wm * PM + x * 16 + cr][0];
+        const v8bf am = *(const v8bf*)&sl.Am[cur][kr][wm * PM + x * 16 + cr][0];
+        const v8bf al = *(const v8bf*)&sl.Al[cur][kr][wm * PM + x * 16 + cr][0];
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bm[y], ah, acc[x][y]);
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bh[y], am, acc[x][y]);
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bl[y], ah, acc[x][y]);
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bh[y], al, acc[x][y]);
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bm[y], am, acc[x][y]);
+#pragma unroll
+        for (int y = 0; y < FN; ++y) acc[x][y] = mfmabf(bh[y], ah, acc[x][y]);
+      }
+    } else if constexpr (P == PREC_BF16X3) {
       v8bf ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
       for (int x = 0; x < FM; ++x) {
@@ -238,7 +318,12 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
           }
       }
     }
-    if (t + 1 < nk) store(cur ^ 1);
+    if constexpr (NBUF == 2) {
+      if (t + 1 < nk) store(cur ^ 1);
+    } else {
+      __syncthreads();  // every wave is done with the single buffer
+      if (t + 1 < nk) store(0);
+    }
     __syncthreads();
   }
   // The MFMA computes D = C^T.  v_mfma_f64_16x16x4f64 leaves D(row =
@@ -391,7 +476,7 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
               8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)));
     return hipGetLastError();
   }
-  const int BK = prec == PREC_BF16X3 ? 32 : 16;
+  const int BK = (prec == PREC_BF16X3 || prec == PREC_BF16X6) ? 32 : 16;
   // 128 x 128 tiles when the output, or the output times a split of K,
   // gives enough workgroups; else 64 x 64.  Long reductions are split over
   // blockIdx.z until about two workgroups per CU are in flight.
@@ -415,7 +500,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     // thin sampling products: 4 splits, not 5).  Otherwise about 512,
     // rounded up (FP32 128 x 128 and 64 x 64 tiles fit more per CU, and the
     // FP32 products keep their shorter FP32 accumulation chains).
-    const bool two_per_cu = shape == 1 && (prec == PREC_BF16X3 || prec == PREC_FP64);
+    const bool two_per_cu =
+        shape == 1 && (prec == PREC_BF16X3 || prec == PREC_BF16X6 || prec == PREC_FP64);
     splits = small ? (1024 + tiles - 1) / tiles
                    : (two_per_cu ? std::max(1, 512 / tiles) : (512 + tiles - 1) / tiles);
     splits = std::min(splits, K / (small ? 256 : 512));
@@ -438,11 +524,13 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     al = 1.0;
     be = 0.0;
   }
-  const int cls = 12 * shape + 4 * (int)prec +
+  const int cls = 16 * shape + 4 * (int)prec +
                   (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN));
   const int slot = prof_mark(st, cls);
   if (prec == PREC_FP32)
     launch_p<PREC_FP32>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else if (prec == PREC_BF16X6)
+    launch_p<PREC_BF16X6>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else if (prec == PREC_BF16X3)
     launch_p<PREC_BF16X3>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else

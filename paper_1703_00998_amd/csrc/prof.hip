@@ -2,6 +2,7 @@
 // around each instrumented kernel (thin GEMMs, split-K reductions, panel QR,
 // small SVDs).  Off unless randutv_profile_begin() was called; not
 // thread-safe (one factorization at a time per process while profiling).
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -23,7 +24,25 @@ int g_suppress = 0;  // > 0 inside a composite region timed as one class
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
+// Events are released when the process exits, before the HIP runtime's
+// own teardown (the handler is registered after the runtime initialised).
+void release_events() {
+  for (auto& r : g_recs) {
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  for (hipEvent_t e : g_pool)
+    if (e) (void)hipEventDestroy(e);
+  g_pool.clear();
+}
+
 hipEvent_t take_event() {
+  static bool registered = false;
+  if (!registered) {
+    std::atexit(release_events);
+    registered = true;
+  }
   if (!g_pool.empty()) {
     hipEvent_t e = g_pool.back();
     g_pool.pop_back();
@@ -42,9 +61,9 @@ std::string class_name(int c) {
   if (c == PC_SVD) return "small_svd";
   if (c == PC_GEMM_SMALL) return "gemm_small_fp64";
   static const char* ops[4] = {"nn", "tn", "nt", "tt"};
-  static const char* precs[3] = {"fp64", "fp32", "bf16x3"};
+  static const char* precs[4] = {"fp64", "fp32", "bf16x3", "bf16x6"};
   static const char* tiles[2] = {"t64", "t128"};
-  return std::string("gemm_") + ops[c % 4] + "_" + precs[(c / 4) % 3] + "_" + tiles[c / 12];
+  return std::string("gemm_") + ops[c % 4] + "_" + precs[(c / 4) % 4] + "_" + tiles[c / 16];
 }
 
 std::vector<std::string> g_names;

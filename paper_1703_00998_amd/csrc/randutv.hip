@@ -21,6 +21,7 @@
 // The lower-triangular form A = U L V^T runs this on A^T.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -34,10 +35,13 @@ namespace {
 
 constexpr int kMaxB = 256;
 constexpr int kMaxPanelRows = kPanelMaxWGGlobal * kPanelMaxRows;
+// Sweep budget of the one-sided Jacobi SVDs.  The zero-padded, rank-deficient
+// factors of over-sampled steps with fewer than b + p rows left need more
+// than 30 sweeps (their near-zero columns keep rotating at rounding level).
 constexpr int kJacobiSweeps = 40;
 
 struct Layout {
-  size_t Y, Vh, Vh2, Vh3, Z, Uh, Uh2, Uh3, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwV3, TwU, TwU2,
+  size_t status, Y, Vh, Vh2, Vh3, Z, Uh, Uh2, Uh3, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwV3, TwU, TwU2,
       TwU3, tauV, tauU, Rst,
       Ust, Vst, D, Jw, Jv, Ftmp, split, nrm, ints, panel, hr, total;
   // Over-sampling (p > 0) only: QR and SVD of the extended sample.
@@ -68,6 +72,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
     off = al256(off + bytes);
     return o;
   };
+  L.status = take(kStatusBytes);  // first: randutv_status reads it at offset 0
   L.Y = take((size_t)n * bp * d);
   L.Vh = take(nb * d);
   L.Vh2 = take(nb * d);
@@ -143,9 +148,32 @@ constexpr int kMaxDevices = 64;
 SideCtx g_side[kMaxDevices];
 std::mutex g_mu;  // one factorization enqueues at a time (shared events)
 
+// The side streams and their events are released when the process exits,
+// before the HIP runtime's own teardown (this handler is registered after
+// the runtime has initialised, so it runs first).
+void release_side() {
+  for (auto& c : g_side) {
+    for (auto& e : c.ev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+    if (c.side) {
+      (void)hipStreamDestroy(c.side);
+      c.side = nullptr;
+    }
+    c.ok = false;
+  }
+}
+
 SideCtx* side_ctx() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  static bool registered = false;  // g_mu is held
+  if (!registered) {
+    std::atexit(release_side);
+    registered = true;
+  }
   SideCtx& c = g_side[dev];
   if (!c.ok) {
     if (!c.side && hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess) {
@@ -256,7 +284,7 @@ __global__ void k_zero_int(int* p) {
 // `iy` holds the size word, the status word and the sweep counters.
 hipError_t oversample_basis(hipStream_t st, int Ni, int B, int Bp, double* Y, int64_t ldy,
                             const Layout& L, char* base, int* iy, const HrWork& hw,
-                            const PanelWork& pw, double* split, size_t se) {
+                            const PanelWork& pw, double* split, size_t se, int* fail) {
   auto dp = [&](size_t off) { return (double*)(base + off); };
   double *VY = dp(L.VY), *TwY = dp(L.TwY), *RY = dp(L.RY), *UR = dp(L.UR), *VR = dp(L.VR),
          *JwR = dp(L.JwR), *JvR = dp(L.JvR), *tauY = dp(L.tauY), *DR = dp(L.DR), *Cy = dp(L.Cy),
@@ -274,7 +302,8 @@ hipError_t oversample_basis(hipStream_t st, int Ni, int B, int Bp, double* Y, in
   hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(64), 0, st, iy, 1, Bp, Bp);
   e = hipGetLastError();
   if (e == hipSuccess)
-    e = batched_svd(st, 1, iy, Bp, RY, bb, UR, VR, bb, DR, Bp, JwR, JvR, iy + 1, kJacobiSweeps);
+    e = batched_svd(st, 1, iy, Bp, RY, bb, UR, VR, bb, DR, Bp, JwR, JvR, iy + 1, kJacobiSweeps,
+                    fail);
   if (e != hipSuccess) return e;
   if (!tall) return copy_matrix(st, Ni, B, UR, Bp, Y, ldy);
   e = set_zero(st, Ni, B, Y, ldy);
@@ -295,14 +324,6 @@ hipError_t oversample_basis(hipStream_t st, int Ni, int B, int Bp, double* Y, in
   } while (0)
 
 }  // namespace
-
-namespace rutv {
-// factor_impl with over-sampling p (b + p samples per randomized step).
-int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,
-                const double* G, int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv,
-                int64_t k_stop, double tol, int prec, unsigned flags, void* work,
-                size_t work_bytes, int64_t* k_out, void* stream, const ApproxTape* tape);
-}  // namespace rutv
 
 extern "C" {
 
@@ -328,7 +349,7 @@ int randutv_workspace_size_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, 
   if (b < 1 || b > kMaxB) return -3;
   if (p < 0 || b + p > kMaxB) return -4;
   if (q < 0 || q > 16) return -5;
-  if (prec < 0 || prec > 3) return -6;
+  if (prec < 0 || prec > kPrecMax) return -6;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -7;
   if (!bytes) return -8;
   *bytes = make_layout(m, n, b, p).total;
@@ -345,10 +366,10 @@ int randutv_workspace_size_lower(int64_t m, int64_t n, int64_t b, int q, int pre
   if (n < 1 || m < 1) return -1;
   if (b < 1 || b > kMaxB) return -3;
   if (q < 0 || q > 16) return -4;
-  if (prec < 0 || prec > 3) return -5;
+  if (prec < 0 || prec > kPrecMax) return -5;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -6;
   if (!bytes) return -7;
-  *bytes = al256((size_t)m * n * sizeof(double)) + make_layout(n, m, b).total;
+  *bytes = make_layout(n, m, b).total + al256((size_t)m * n * sizeof(double));
   return 0;
 }
 
@@ -357,7 +378,7 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, uns
   if (n < 1 || m < 1) return -1;
   if (b < 1 || b > kMaxB) return -3;
   if (q < 0 || q > 16) return -4;
-  if (prec < 0 || prec > 3) return -5;
+  if (prec < 0 || prec > kPrecMax) return -5;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -6;
   if (!bytes) return -7;
   *bytes = make_layout(m, n, b).total;
@@ -395,24 +416,32 @@ int randutv_factor_lower(int64_t m, int64_t n, int64_t b, int q, double* T, int6
   if (randutv_g_cols(n, m, b) > 0 && (!G || ldg < n)) return -5;
   if ((flags & RANDUTV_FORM_U) && (!U || ldu < m)) return -6;
   if ((flags & RANDUTV_FORM_V) && (!V || ldv < n)) return -7;
-  if (prec < 0 || prec > 3) return -10;
+  if (prec < 0 || prec > kPrecMax) return -10;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -11;
   if (!work || ((uintptr_t)work & 255)) return -12;
   size_t need = 0;
   randutv_workspace_size_lower(m, n, b, q, prec, flags, &need);
   if (work_bytes < need) return RANDUTV_E_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
-  double* Tt = (double*)work;  // A^T, n x m
-  const size_t tb = al256((size_t)m * n * sizeof(double));
+  // The inner factorization's workspace comes first (its status words at
+  // offset 0), then A^T (n x m).
+  const size_t fb = make_layout(n, m, b).total;
+  double* Tt = (double*)((char*)work + fb);
   HIPCHK(transpose(st, (int)m, (int)n, T, ldt, Tt, n));
   // A^T = U' T' V'^T, so A = V' T'^T U'^T: U of A^T goes to V, V of A^T to U.
+  // The inner call only enqueues; its status is read after the transpose back.
   const int r = rutv::factor_core(n, m, b, 0, q, Tt, n, G, ldg, V, ldv, U, ldu, k_stop, tol, prec,
-                                  swap_uv(flags), (char*)work + tb, work_bytes - tb, k_out, stream,
-                                  nullptr);
+                                  swap_uv(flags), work, fb, nullptr, stream, nullptr, true);
   if (r < 0) return r;
   HIPCHK(transpose(st, (int)n, (int)m, Tt, n, T, ldt));
-  if (k_out) HIPCHK(hipStreamSynchronize(st));
-  return r;
+  if (k_out) return read_status(work, k_out, st);
+  return 0;
+}
+
+int randutv_status(const void* work, size_t work_bytes, int64_t* k_out, void* stream) {
+  if (!work || ((uintptr_t)work & 255)) return -1;
+  if (work_bytes < kStatusBytes) return -2;
+  return read_status(work, k_out, (hipStream_t)stream);
 }
 
 int randutv_factor_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,
@@ -420,7 +449,7 @@ int randutv_factor_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* 
                      int64_t ldv, int64_t k_stop, double tol, int prec, unsigned flags,
                      void* work, size_t work_bytes, int64_t* k_out, void* stream) {
   return rutv::factor_core(m, n, b, p, q, T, ldt, G, ldg, U, ldu, V, ldv, k_stop, tol, prec, flags,
-                     work, work_bytes, k_out, stream, nullptr);
+                     work, work_bytes, k_out, stream, nullptr, true);
 }
 }  // extern "C"
 
@@ -433,13 +462,14 @@ int factor_impl(int64_t m, int64_t n, int64_t b, int q, double* T, int64_t ldt, 
                 double tol, int prec, unsigned flags, void* work, size_t work_bytes,
                 int64_t* k_out, void* stream, const ApproxTape* tape) {
   return factor_core(m, n, b, 0, q, T, ldt, G, ldg, U, ldu, V, ldv, k_stop, tol, prec, flags, work,
-                     work_bytes, k_out, stream, tape);
+                     work_bytes, k_out, stream, tape, true);
 }
 
 int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, int64_t ldt,
                 const double* G, int64_t ldg, double* U, int64_t ldu, double* V, int64_t ldv,
                 int64_t k_stop, double tol, int prec, unsigned flags, void* work,
-                size_t work_bytes, int64_t* k_out, void* stream, const ApproxTape* tape) {
+                size_t work_bytes, int64_t* k_out, void* stream, const ApproxTape* tape,
+                bool use_side) {
   if (m < 1 || n < 1) return -1;
   if (m < n && tape) return RANDUTV_E_UNSUPPORTED;  // the approximation takes m >= n
   if (p > 0 && tape) return RANDUTV_E_UNSUPPORTED;
@@ -453,7 +483,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   const bool formU = flags & RANDUTV_FORM_U, formV = flags & RANDUTV_FORM_V;
   if (formU && (!U || ldu < m)) return -6;
   if (formV && (!V || ldv < n)) return -7;
-  if (prec < 0 || prec > 3) return -10;
+  if (prec < 0 || prec > kPrecMax) return -10;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -11;
   if (!work || ((uintptr_t)work & 255)) return -12;
   const Layout L = make_layout(m, n, b, p);
@@ -476,15 +506,18 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   panel_work_carve(base + L.panel, (int)(b + p), &pw);
   HrWork hw;
   hr_work_carve(base + L.hr, std::max(m, n), (int)(b + p), &hw);
+  // The status words live at the start of the workspace; the panel kernels'
+  // spin-limit flag is one of them.
+  StatusBlock* blk = (StatusBlock*)(base + L.status);
+  pw.err = &blk->sync_err;
   // Arithmetic of the sampling products (ps) and of the trailing updates (pu).
-  const Prec ps = prec == kPrecMixed ? PREC_BF16X3 : (Prec)prec;
-  const Prec pu = prec == kPrecMixed ? PREC_FP32 : (Prec)prec;
+  const Prec ps = sampling_prec(prec);
+  const Prec pu = update_prec(prec);
   const size_t se = L.split_elems;
   const int M = (int)m, N = (int)n, B = (int)b;
   const int Bp = (int)(b + p);    // samples per randomized step
   const int MN = std::max(M, N);  // leading dimension of the U / V stream products
   int* intsY = p > 0 ? (int*)(base + L.intsY) : nullptr;
-  int nrand = 0;  // randomized steps taken
 
   double* const VhS[kSlots] = {dp(L.Vh), dp(L.Vh2), dp(L.Vh3)};
   double* const UhS[kSlots] = {dp(L.Uh), dp(L.Uh2), dp(L.Uh3)};
@@ -492,10 +525,12 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   double* const TwUS[kSlots] = {dp(L.TwU), dp(L.TwU2), dp(L.TwU3)};
   constexpr int kVR = 0, kUR = kSlots, kVD = 2 * kSlots, kUD = 3 * kSlots, kJoin = 4 * kSlots;
 
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, pw.err);
+  HIPCHK(status_init(st, blk));
   if (formU) HIPCHK(set_identity(st, M, M, U, ldu));
   if (formV) HIPCHK(set_identity(st, N, N, V, ldv));
-  SideCtx* sc = (formU || formV) ? side_ctx() : nullptr;
+  // Without the second stream (use_side false) U and V are updated on the
+  // caller's stream, in the same launches.
+  SideCtx* sc = (use_side && (formU || formV)) ? side_ctx() : nullptr;
   const hipStream_t ss = sc ? sc->side : st;  // U / V stream (the main one if none)
   bool vpend[kSlots] = {}, upend[kSlots] = {};
   if (sc) {
@@ -526,7 +561,8 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     normA = std::sqrt(h);
   }
 
-  std::vector<int> widths;
+  // Blocks whose R goes to the batched SVD: all b wide except possibly the last.
+  int nsvd = 0, last_w = B;
   int64_t k_done = std::min(m, n);
   for (int64_t i = 0; i < s; ++i) {
     const int r0 = (int)(i * b);
@@ -552,12 +588,11 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
         HIPCHK(gemm(st, ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
       }
       if (p > 0) HIPCHK(oversample_basis(st, Ni, B, Bp, Y, N, L, base, intsY + (size_t)i * kIntsY,
-                                         hw, pw, split, se));
-      ++nrand;
-      // [Vq, ~] = qr(Y)
+                                         hw, pw, split, se, &blk->svd_fail));
+      // Householder QR of Y: the right transform's reflectors.
       HIPCHK(reclaim(kVD + sl, vpend[sl]));
       HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, RV, B, tauV, TwV, B, hw, pw, split, se));
-      // T(:, J) = T(:, J) Vq, all m rows.
+      // Right transform of T's trailing columns, all m rows.
       double* TJ = T + (int64_t)r0 * ldt;
       HIPCHK(gemm(st, pu, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
       HIPCHK(gemm(st, PREC_FP64, false, false, M, B, B, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
@@ -570,7 +605,8 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
         HIPCHK(gemm_side(ss, false, true, N, Ni, B, -1.0, W2s, MN, Vh, N, 1.0, VJ, ldv, kSideChunkUpd));
         HIPCHK(side_done(kVD + sl, &vpend[sl]));
       }
-      // [Uq, R] = qr(T([I2,I3], J2))
+      // Householder QR of the new block column (rows I2, I3): the left
+      // transform's reflectors and the diagonal block's R.
       // (The panel is read in place; T([I2,I3], J2) is overwritten below.)
       HIPCHK(reclaim(kUD + sl, upend[sl]));
       HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, M, RU, B, tauU, TwU, B, hw, pw, split, se));
@@ -592,7 +628,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       // T([I2,I3], J2) = [R; 0]; R moves to the stash, the diagonal block is
       // written from the SVD after the loop.
       HIPCHK(set_zero(st, Mi, B, X, ldt));
-      widths.push_back(B);
+      ++nsvd;
       bool stop = k_stop > 0 && r0 + B >= k_stop;
       if (!stop && tol > 0.0) {
         HIPCHK(sumsq(st, Mi - B, Ni - B, X + B + (int64_t)B * ldt, ldt, nrm + 16, nrm + 1));
@@ -622,7 +658,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       hipLaunchKernelGGL(k_transpose, dim3(grid_blocks((int64_t)c * c)), dim3(256), 0, st, c, c,
                          Ftmp, (int64_t)c, RU, (int64_t)B);
       HIPCHK(hipGetLastError());
-      if (r0 > 0) {  // T(I1, J) = T(I1, J) H
+      if (r0 > 0) {  // the rows above the block, times H
         HIPCHK(gemm(st, PREC_FP64, false, false, r0, c, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
         HIPCHK(gemm(st, PREC_FP64, false, false, r0, c, c, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
         HIPCHK(gemm(st, PREC_FP64, false, true, r0, Ni, c, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
@@ -636,7 +672,8 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
         HIPCHK(side_done(kVD + sl, &vpend[sl]));
       }
       HIPCHK(set_zero(st, Mi, Ni, X, ldt));
-      widths.push_back(c);
+      ++nsvd;
+      last_w = c;
       k_done = M;
     } else {
       // Last block: economic SVD via Householder QR of T([I2,I3],[J2,J3]).
@@ -653,7 +690,8 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
         HIPCHK(side_done(kUD + sl, &upend[sl]));
       }
       HIPCHK(set_zero(st, Mi, c, X, ldt));
-      widths.push_back(c);
+      ++nsvd;
+      last_w = c;
       k_done = n;
     }
   }
@@ -665,6 +703,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   };
   if (tape) {  // truncated approximation: no small SVDs (U_k U_k^T does not see them)
     HIPCHK(join_side());
+    HIPCHK(status_done(st, blk, k_done));
     if (k_out) *k_out = k_done;
     return 0;
   }
@@ -673,12 +712,12 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.  The SVDs and T's part run
   // while the U / V stream finishes its last products; U and V's part
   // waits for it.
-  const int nsvd = (int)widths.size();
-  hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(256), 0, st, nbs, nsvd, B, widths.back());
+  auto width = [&](int i) { return i == nsvd - 1 ? last_w : B; };
+  hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(256), 0, st, nbs, nsvd, B, last_w);
   HIPCHK(batched_svd(st, nsvd, nbs, B, Rst, (int64_t)B * B, Ust, Vst, (int64_t)B * B, Dd, B, Jw, Jv,
-                     jstatus, kJacobiSweeps));
+                     jstatus, kJacobiSweeps, &blk->svd_fail));
   for (int i = 0; i < nsvd; ++i) {
-    const int r0 = i * B, w = widths[i];
+    const int r0 = i * B, w = width(i);
     const double* Us = Ust + (size_t)i * B * B;
     const double* Vs = Vst + (size_t)i * B * B;
     double* X = T + r0 + (int64_t)r0 * ldt;
@@ -697,7 +736,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   }
   HIPCHK(join_side());
   for (int i = 0; i < nsvd && (formU || formV); ++i) {
-    const int r0 = i * B, w = widths[i];
+    const int r0 = i * B, w = width(i);
     const double* Us = Ust + (size_t)i * B * B;
     const double* Vs = Vst + (size_t)i * B * B;
     if (formU) {
@@ -711,22 +750,10 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       HIPCHK(copy_matrix(st, N, w, Ftmp, N, blk, ldv));
     }
   }
+  HIPCHK(status_done(st, blk, k_done));
   if (k_out) {
     *k_out = k_done;
-    HIPCHK(hipStreamSynchronize(st));
-    int err = 0;
-    HIPCHK(hipMemcpy(&err, pw.err, sizeof(int), hipMemcpyDeviceToHost));
-    if (err) return RANDUTV_E_SYNC;
-    std::vector<int> js(nsvd);
-    HIPCHK(hipMemcpy(js.data(), jstatus, nsvd * sizeof(int), hipMemcpyDeviceToHost));
-    for (int v : js)
-      if (v < 0) return 1;
-    if (p > 0 && nrand > 0) {  // the SVDs of the extended samples
-      std::vector<int> ys((size_t)nrand * kIntsY);
-      HIPCHK(hipMemcpy(ys.data(), intsY, ys.size() * sizeof(int), hipMemcpyDeviceToHost));
-      for (int i = 0; i < nrand; ++i)
-        if (ys[(size_t)i * kIntsY + 1] < 0) return 1;
-    }
+    return read_status(base, nullptr, st);
   }
   return 0;
 }
@@ -738,7 +765,9 @@ extern "C" {
 int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha,
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                  double* C, int64_t ldc, void* work, size_t work_bytes, void* stream) {
-  if (prec < 0 || prec > 2) return -1;
+  // Arithmetic: RANDUTV_FP64, _FP32, _BF16X3, or 4 for BF16x6.
+  if (prec < 0 || prec > 4 || prec == 3) return -1;
+  const Prec gp = prec == 4 ? PREC_BF16X6 : (Prec)prec;
   if (M < 0 || M > INT32_MAX) return -4;
   if (N < 0 || N > INT32_MAX) return -5;
   if (K < 0 || K > INT32_MAX) return -6;
@@ -748,7 +777,7 @@ int randutv_gemm(int prec, int ta, int tb, int64_t M, int64_t N, int64_t K, doub
     if (!B || ldb < std::max<int64_t>(1, brows)) return -10;
   }
   if (M > 0 && N > 0 && (!C || ldc < M)) return -13;
-  hipError_t e = gemm((hipStream_t)stream, (Prec)prec, ta != 0, tb != 0, (int)M, (int)N, (int)K,
+  hipError_t e = gemm((hipStream_t)stream, gp, ta != 0, tb != 0, (int)M, (int)N, (int)K,
                       alpha, A, lda, B, ldb, beta, C, ldc, (double*)work,
                       work ? work_bytes / sizeof(double) : 0);
   return e == hipSuccess ? 0 : RANDUTV_E_HIP - (int)e;
@@ -825,7 +854,7 @@ int randutv_small_svd(int64_t count, const int* nbs, int64_t ld, const double* R
   hipError_t e = hipMemcpyAsync(ints, nbs, count * sizeof(int), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = batched_svd(st, (int)count, ints, (int)ld, R, ld * ld, Us, Vs, ld * ld, D, ld, Jw, Jv,
-                    ints + count, kJacobiSweeps);
+                    ints + count, kJacobiSweeps, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return RANDUTV_E_HIP - (int)e;
   std::vector<int> js(count);

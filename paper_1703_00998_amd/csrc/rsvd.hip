@@ -20,12 +20,12 @@ namespace {
 
 constexpr int kMaxC = 256;  // k + p: one panel and one Jacobi block
 constexpr int kMaxRows = kPanelMaxWGGlobal * kPanelMaxRows;
-constexpr int kSweeps = 40;
+constexpr int kSweeps = 40;  // Jacobi sweep budget
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct RsvdLayout {
-  size_t Y, Z, VY, Q, B, VB, TwY, TwB, RB, Cq, UR, VR, Jw, Jv, Dw, C1, C2, tauY, tauB, ints,
+  size_t status, Y, Z, VY, Q, B, VB, TwY, TwB, RB, Cq, UR, VR, Jw, Jv, Dw, C1, C2, tauY, tauB, ints,
       panel, hr, split, total;
   size_t split_elems;
 };
@@ -39,6 +39,7 @@ RsvdLayout rsvd_layout(int64_t m, int64_t n, int64_t k, int64_t c) {
     off = al256(off + bytes);
     return o;
   };
+  L.status = take(kStatusBytes);  // first: randutv_status reads it at offset 0
   L.Y = take((size_t)n * c * d);
   L.Z = take((size_t)m * c * d);
   L.VY = take((size_t)n * c * d);
@@ -67,11 +68,8 @@ RsvdLayout rsvd_layout(int64_t m, int64_t n, int64_t k, int64_t c) {
   return L;
 }
 
-__global__ void k_rsvd_init(int* err, int* nbs, int c) {
-  if (threadIdx.x == 0) {
-    err[0] = 0;
-    nbs[0] = c;
-  }
+__global__ void k_rsvd_init(int* nbs, int c) {
+  if (threadIdx.x == 0) nbs[0] = c;
 }
 
 int check_args(int64_t m, int64_t n, int64_t k, int64_t p, int q, int prec) {
@@ -79,7 +77,7 @@ int check_args(int64_t m, int64_t n, int64_t k, int64_t p, int q, int prec) {
   if (k < 1) return -3;
   if (p < 0 || k + p > kMaxC || k + p > std::min(m, n)) return -4;
   if (q < 0 || q > 16) return -5;
-  if (prec < 0 || prec > 3) return -15;
+  if (prec < 0 || prec > kPrecMax) return -15;
   if (std::max(m, n) > kMaxRows || m * n > ((int64_t)1 << 40)) return RANDUTV_E_UNSUPPORTED;
   return 0;
 }
@@ -132,13 +130,16 @@ int randutv_rsvd(int64_t m, int64_t n, int64_t k, int64_t p, int q, const double
   panel_work_carve(base + L.panel, (int)c64, &pw);
   HrWork hw;
   hr_work_carve(base + L.hr, std::max(m, n), (int)c64, &hw);
+  StatusBlock* blk = (StatusBlock*)(base + L.status);
+  pw.err = &blk->sync_err;
   const size_t se = L.split_elems;
-  const Prec ps = prec == kPrecMixed ? PREC_BF16X3 : (Prec)prec;  // sampling products
-  const Prec pu = prec == kPrecMixed ? PREC_FP32 : (Prec)prec;    // B = A Q
+  const Prec ps = sampling_prec(prec);  // sampling products
+  const Prec pu = update_prec(prec);    // B = A Q
   const int M = (int)m, N = (int)n, K = (int)k, C = (int)c64;
   const int64_t cc = (int64_t)C * C;
 
-  hipLaunchKernelGGL(k_rsvd_init, dim3(1), dim3(64), 0, st, pw.err, ints, C);
+  RCHK(status_init(st, blk));
+  hipLaunchKernelGGL(k_rsvd_init, dim3(1), dim3(64), 0, st, ints, C);
   RCHK(hipGetLastError());
   // Range finder: Y = (A^T A)^q A^T G, Q = Householder Q factor of Y.
   RCHK(gemm(st, ps, true, false, N, C, M, 1.0, A, lda, G, ldg, 0.0, Y, N, split, se));
@@ -154,7 +155,8 @@ int randutv_rsvd(int64_t m, int64_t n, int64_t k, int64_t p, int q, const double
   // Stage two: B = A Q; B = Q_B R_B; R_B = U_R D W^T.
   RCHK(gemm(st, pu, false, false, M, C, N, 1.0, A, lda, Q, N, 0.0, Bm, M, split, se));
   RCHK(panel_qr_hr(st, M, C, Bm, M, VB, M, RB, C, tauB, TwB, C, hw, pw, split, se));
-  RCHK(batched_svd(st, 1, ints, C, RB, cc, UR, VR, cc, Dw, C, Jw, Jv, ints + 1, kSweeps));
+  RCHK(batched_svd(st, 1, ints, C, RB, cc, UR, VR, cc, Dw, C, Jw, Jv, ints + 1, kSweeps,
+                   &blk->svd_fail));
   // U = Q_B [U_R(:, 0:K); 0] = U1 - V_B (Tw_B (V_B(0:C, :)^T U_R(:, 0:K)))
   RCHK(set_zero(st, M, K, U, ldu));
   RCHK(copy_matrix(st, C, K, UR, C, U, ldu));
@@ -164,14 +166,11 @@ int randutv_rsvd(int64_t m, int64_t n, int64_t k, int64_t p, int q, const double
   // V = Q W(:, 0:K), D = the K largest singular values.
   RCHK(gemm(st, PREC_FP64, false, false, N, K, C, 1.0, Q, N, VR, C, 0.0, V, ldv, split, se));
   RCHK(hipMemcpyAsync(D, Dw, (size_t)K * sizeof(double), hipMemcpyDeviceToDevice, st));
+  RCHK(status_done(st, blk, K));
   if (sweeps_out) {
-    RCHK(hipStreamSynchronize(st));
-    int hst[2] = {0, 0};
-    RCHK(hipMemcpy(hst, pw.err, sizeof(int), hipMemcpyDeviceToHost));
-    if (hst[0]) return RANDUTV_E_SYNC;
-    RCHK(hipMemcpy(hst + 1, ints + 1, sizeof(int), hipMemcpyDeviceToHost));
-    *sweeps_out = hst[1];
-    if (hst[1] < 0) return 1;
+    const int r = read_status(work, nullptr, st);
+    RCHK(hipMemcpy(sweeps_out, ints + 1, sizeof(int), hipMemcpyDeviceToHost));
+    return r;
   }
   return 0;
 }

@@ -1,5 +1,5 @@
-// SVD of the small diagonal blocks (Figure "The algorithm randUTV":
-// [Us, Ds, Vs] = svd(R(1:b,1:b)); Section 2.4 eq. smallSVD).
+// SVD of the small diagonal blocks (Figure "The algorithm randUTV": the SVD
+// of each step's b x b block R; Section 2.4 eq. smallSVD).
 //
 // One-sided (Hestenes) Jacobi: columns of W = R are rotated pairwise until
 // mutually orthogonal, accumulating the rotations in V; then sigma_j =
@@ -14,7 +14,9 @@
 // does; waves take disjoint pairs.  Blocks stay in place in global memory, so
 // the kernel boundary between rounds is the only synchronization.  A sweep
 // is nblk-1 rounds; the SVDs of all randUTV steps advance together (grid.y
-// = matrix), and a matrix stops as soon as a whole sweep rotated nothing.
+// = matrix), and a matrix stops as soon as a whole sweep rotated nothing:
+// later rounds see that on the device and return at once, so the host
+// enqueues the whole sweep budget without waiting.
 //
 // Output conventions: sigma descending (ties by index); each (u_j, v_j)
 // flipped so the largest-magnitude entry of v_j is positive (first index on
@@ -22,7 +24,6 @@
 // e_1, e_2, ...  Matrices wider than kMaxLdsN use a single-workgroup
 // global-memory kernel.
 #include <algorithm>
-#include <mutex>
 
 #include "common.h"
 
@@ -33,9 +34,6 @@ constexpr int MAXN = 1024;
 constexpr int kBW = 16;          // Jacobi block width
 constexpr int kRoundThreads = 64 * kBW;  // one wave per column pair of a sub-round
 constexpr int kMaxLdsN = 256;    // largest order handled by the LDS block kernel
-constexpr int kFirstSweeps = 6;  // block-Jacobi sweeps launched before the first convergence check
-constexpr int kMoreSweeps = 2;   // and between later checks
-constexpr int kMaxPollDevices = 64;
 
 // DPP move of a double (two 32-bit halves) with control CTRL.
 template <int CTRL>
@@ -303,7 +301,8 @@ __global__ __launch_bounds__(256) void k_bj_finish(const int* __restrict__ nbs, 
                                                    double* __restrict__ Vs,
                                                    double* __restrict__ D, int64_t strideD,
                                                    const int* __restrict__ rotcount,
-                                                   int max_sweeps, int* __restrict__ status) {
+                                                   int max_sweeps, int* __restrict__ status,
+                                                   int* __restrict__ fail) {
   __shared__ double sig[kMaxLdsN];
   __shared__ int rank[kMaxLdsN];
   const int mi = blockIdx.x;
@@ -318,7 +317,9 @@ __global__ __launch_bounds__(256) void k_bj_finish(const int* __restrict__ nbs, 
         st = s + 1;
         break;
       }
-    status[mi] = nb <= 1 ? 0 : st;
+    if (nb <= 1) st = 0;
+    status[mi] = st;
+    if (st < 0 && fail) atomicOr(fail, 1);
   }
 }
 
@@ -329,7 +330,8 @@ __global__ __launch_bounds__(256) void k_jacobi(const int* __restrict__ nbs, int
                                                 double* __restrict__ Vs, int64_t strideUV,
                                                 double* __restrict__ D, int64_t strideD,
                                                 double* __restrict__ Wk, double* __restrict__ Vk,
-                                                int* __restrict__ status, int max_sweeps) {
+                                                int* __restrict__ status, int max_sweeps,
+                                                int* __restrict__ fail) {
   __shared__ double sig[MAXN];
   __shared__ int rank[MAXN];
   __shared__ int rotated;
@@ -373,20 +375,24 @@ __global__ __launch_bounds__(256) void k_jacobi(const int* __restrict__ nbs, int
     __syncthreads();
   }
   finish_svd(nb, ld, W, V, Us + mi * strideUV, Vs + mi * strideUV, D + mi * strideD, sig, rank);
-  if (tid == 0) status[mi] = conv ? sweeps : -1;
+  if (tid == 0) {
+    status[mi] = conv ? sweeps : -1;
+    if (!conv && fail) atomicOr(fail, 1);
+  }
 }
 
 }  // namespace
 
 hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, const double* R,
                        int64_t strideR, double* Us, double* Vs, int64_t strideUV, double* D,
-                       int64_t strideD, double* Wk, double* Vk, int* status, int max_sweeps) {
+                       int64_t strideD, double* Wk, double* Vk, int* status, int max_sweeps,
+                       int* fail) {
   if (count <= 0) return hipSuccess;
   if (ld > MAXN) return hipErrorInvalidValue;
   const int slot = prof_mark(st, PC_SVD);
   if (ld > kMaxLdsN) {
     hipLaunchKernelGGL(k_jacobi, dim3(count), dim3(256), 0, st, nb_dev, ld, R, strideR, Us, Vs,
-                       strideUV, D, strideD, Wk, Vk, status, max_sweeps);
+                       strideUV, D, strideD, Wk, Vk, status, max_sweeps, fail);
     prof_done(st, slot, PC_SVD, 0.0, 0.0);
     return hipGetLastError();
   }
@@ -404,71 +410,17 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
                      strideUV, rotcount, max_sweeps);
   const int nblk = (ld + kBW - 1) / kBW;
   const int nblk2 = nblk + (nblk & 1);
-  // Sweeps go out in groups (kFirstSweeps, then kMoreSweeps at a time); after
-  // each group the host reads the last sweep's rotation counts and stops
-  // once every matrix had a sweep without rotations.  A converged matrix
-  // skips later rounds on the device anyway; this saves the launches.
-  // The counts come back through pinned host memory and an event that the
-  // host polls (a blocking stream synchronization wakes up milliseconds late).
-  // Pinned buffer and event are kept per device between calls (allocating
-  // pinned memory costs far more than one small SVD); calls that poll on
-  // one device take turns.
-  struct Poll {
-    int* last = nullptr;
-    int cap = 0;
-    hipEvent_t ev = nullptr;
-    std::mutex mu;
-  };
-  static Poll polls[kMaxPollDevices];
-  int dev = 0;
-  const bool dev_ok = hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxPollDevices;
-  std::unique_lock<std::mutex> lock;
-  int* last = nullptr;
-  hipEvent_t ev = nullptr;
-  if (dev_ok) {
-    Poll& pl = polls[dev];
-    lock = std::unique_lock<std::mutex>(pl.mu);
-    if (pl.cap < count) {
-      if (pl.last) (void)hipHostFree(pl.last);
-      pl.last = nullptr;
-      pl.cap = 0;
-      if (hipHostMalloc((void**)&pl.last, (size_t)count * sizeof(int), hipHostMallocDefault) ==
-          hipSuccess)
-        pl.cap = count;
-      else
-        pl.last = nullptr;
-    }
-    if (!pl.ev && hipEventCreateWithFlags(&pl.ev, hipEventDisableTiming) != hipSuccess)
-      pl.ev = nullptr;
-    last = pl.last;
-    ev = pl.ev;
-  }
-  const bool check = last && ev;
-  (void)hipGetLastError();
-  hipError_t e = hipSuccess;
-  for (int sw0 = 0; sw0 < max_sweeps && e == hipSuccess;) {
-    const int sw1 = !check ? max_sweeps
-                           : std::min(max_sweeps, sw0 + (sw0 == 0 ? kFirstSweeps : kMoreSweeps));
-    for (int sw = sw0; sw < sw1; ++sw)
-      for (int r = 0; r < nblk2 - 1; ++r)
-        hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st, nb_dev, ld, Wk,
-                           Vk, strideUV, rotcount, max_sweeps, sw, r);
-    sw0 = sw1;
-    if (sw0 >= max_sweeps) break;
-    e = hipMemcpy2DAsync(last, sizeof(int), rotcount + sw0 - 1, (size_t)max_sweeps * sizeof(int),
-                         sizeof(int), count, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipEventRecord(ev, st);
-    if (e != hipSuccess) break;
-    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
-    }
-    if (e != hipSuccess) break;
-    bool done = true;
-    for (int i = 0; i < count; ++i) done = done && last[i] == 0;
-    if (done) break;
-  }
-  if (e != hipSuccess) return e;
+  // The whole sweep budget is enqueued and the convergence decision is taken
+  // on the device: a matrix whose last sweep rotated nothing skips every
+  // later round (its workgroups return at once), and k_bj_finish reports a
+  // matrix that still rotated in the last sweep of the budget.  The host
+  // never waits for the device here.
+  for (int sw = 0; sw < max_sweeps; ++sw)
+    for (int r = 0; r < nblk2 - 1; ++r)
+      hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st,
+                         nb_dev, ld, Wk, Vk, strideUV, rotcount, max_sweeps, sw, r);
   hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(256), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
-                     Vs, D, strideD, rotcount, max_sweeps, status);
+                     Vs, D, strideD, rotcount, max_sweeps, status, fail);
   prof_done(st, slot, PC_SVD, 0.0, 0.0);
   return hipGetLastError();
 }

@@ -91,7 +91,7 @@ def test_workspace_and_argument_validation(lib):
     assert call(ldg=10) == -5
     assert call(flags=1) == -6         # U requested but NULL
     assert call(flags=2) == -7
-    assert call(prec=4) == -10
+    assert call(prec=5) == -10
     assert call(flags=8) == -11
     assert call() == -12               # no workspace
     assert call(work=vp(4096 + 8)) == -12   # misaligned

@@ -51,21 +51,23 @@ def test_gemm_fp64_matches_numpy(B, M, N, K, ta, tb):
     np.testing.assert_allclose(got, ref, rtol=0, atol=scale * (np.abs(ref).max() + 1))
 
 
-SPLIT_TOL = {"fp32": 2 ** -24, "bf16x3": 2 ** -16}
+SPLIT_TOL = {"fp32": 2 ** -24, "bf16x3": 2 ** -16, "bf16x6": 2 ** -24}
 
 
 @pytest.mark.parametrize("M,N,K", GEMM_SHAPES)
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
 def test_gemm_split_precision_error_bound(B, M, N, K, ta, tb, prec):
     """Split-precision products (FP64 in and out): each entry's error is
     bounded by a few units of the arithmetic's rounding times |a_i||b_j|
     (FP32: operand rounding 2^-24 plus FP32 accumulation; BF16x3: the dropped
-    lo*lo term and the BF16 representation error, 2^-16 together), plus the
-    accumulation's sqrt(K) growth.  A lane-layout or hi/lo mistake gives
-    errors of order |a_i||b_j| and fails."""
+    lo*lo term and the BF16 representation error, 2^-16 together; BF16x6:
+    three pieces carry x32's 24 bits, and the dropped m*l, l*m, l*l terms are
+    below 2^-23), plus the accumulation's sqrt(K) growth.  A lane-layout or
+    piece mistake gives errors of order |a_i||b_j| (or 2^-8, 2^-16 of it)
+    and fails."""
     print(f"gemm {prec} M={M} N={N} K={K} ta={ta} tb={tb}", flush=True)
-    rng = np.random.default_rng(M * 5 + N * 11 + K + (7 if prec == "fp32" else 13))
+    rng = np.random.default_rng(M * 5 + N * 11 + K + {"fp32": 7, "bf16x3": 13, "bf16x6": 17}[prec])
     A = rng.standard_normal((K, M) if ta else (M, K))
     Bm = rng.standard_normal((N, K) if tb else (K, N))
     A *= np.exp(rng.uniform(-3, 3, size=A.shape))  # spread of magnitudes
@@ -85,6 +87,9 @@ def test_gemm_split_precision_error_bound(B, M, N, K, ta, tb, prec):
     if prec == "bf16x3" and K >= 16:
         # much better than one BF16 product: the error must sit well below 2^-9
         assert float((err / (0.75 * scale + 1e-300)).max()) < 2 ** -12
+    if prec == "bf16x6" and K >= 16:
+        # FP32-like: below the BF16x3 split's 2^-16 (a dropped m*m or h*l term fails)
+        assert float((err / (0.75 * scale + 1e-300)).max()) < 2 ** -17
 
 
 def _larft(V, tau):
@@ -163,7 +168,7 @@ def _stack(mats, ld):
 
 
 def test_small_svd_matches_numpy(B):
-    """[Us, Ds, Vs] = svd(R) of Figure randUTV: singular values against LAPACK,
+    """The small SVD of Figure randUTV: singular values against LAPACK,
     Us diag(D) Vs^T = R, orthogonality, canonical signs."""
     rng = np.random.default_rng(4)
     sizes = [1, 2, 5, 32, 33, 64, 128, 256]
@@ -264,3 +269,47 @@ def test_panel_qr_backward_stable_on_hard_panels(B, case):
     assert orth < 1e-14 and res < 1e-14, (orth, res)
     # kappa > ~3e6 must go column by column; well-conditioned panels must not
     assert fallback == (case not in ("sampling_c3", "gaussian", "scaled_1e150"))
+
+
+@pytest.mark.parametrize("case", ["graded_8000x256", "near_dup_200_3000x256"])
+def test_panel_qr_nb256_fallback_matches_dgeqrf(B, case):
+    """Panels 256 wide are two 128-column blocks on the reconstruction path;
+    an ill-conditioned one goes to the column-by-column kernel on all 256
+    columns, whether the first block already flags (graded columns, kappa ~
+    1e14) or only the second (a near-duplicate column at index 200).  The
+    result is LAPACK's dgeqrf factorization (Section 2.4, eq. unpivQR):
+    R, tau and the reflectors agree elementwise wherever they are well
+    determined (all columns for the graded panel, whose QR only rescales
+    R's columns; the 200 columns before the near-duplicate one), and the
+    compact-WY product stays orthogonal and reproduces the panel."""
+    rng = np.random.default_rng(2)
+    if case == "graded_8000x256":
+        P0 = rng.standard_normal((8000, 256)) * np.exp(-np.arange(256) / 8.0)
+        ncmp = 256
+    else:
+        P0 = rng.standard_normal((3000, 256))
+        P0[:, 200] = 3 * P0[:, 199] + 1e-12 * rng.standard_normal(3000)
+        ncmp = 200
+    Mp, nb = P0.shape
+    dP = B.colmajor(P0)
+    dtau = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    dTw = B.colmajor(np.zeros((nb, nb)))
+    fallback = B.randutv_panel_qr(dP, dtau, dTw)
+    torch.cuda.synchronize()
+    assert fallback
+    qr, tau_ref, _, info = scipy.linalg.lapack.dgeqrf(np.asfortranarray(P0))
+    assert info == 0
+    P, tau, T = _np(dP), _np(dtau), _np(dTw)
+    R, Rr = np.triu(P[:nb]), np.triu(qr[:nb])
+    V, Vr = np.tril(P, -1)[:, :nb], np.tril(qr, -1)[:, :nb]
+    scale = np.abs(Rr).max(axis=0)  # column scale of R
+    np.testing.assert_allclose(R[:, :ncmp] / scale[:ncmp], Rr[:, :ncmp] / scale[:ncmp],
+                               rtol=0, atol=1e-12)
+    np.testing.assert_allclose(tau[:ncmp], tau_ref[:ncmp], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(V[:, :ncmp], Vr[:, :ncmp], rtol=0, atol=1e-11)
+    Vf = V + np.eye(Mp, nb)
+    X = rng.standard_normal((Mp, 8))
+    HX = X - Vf @ (T @ (Vf.T @ X))
+    assert np.abs(HX.T @ HX - X.T @ X).max() / np.abs(X.T @ X).max() < 1e-14
+    Q = np.eye(Mp, nb) - Vf @ (T @ Vf[:nb].T)
+    assert np.linalg.norm(P0 - Q @ R) / np.linalg.norm(P0) < 1e-14

@@ -1,0 +1,98 @@
+"""The boundary only enqueues: randutv_factor / randutv_rsvd with k_out or
+sweeps_out NULL return before the device has finished, and leave their
+status in the first 256 bytes of the workspace, where randutv_status reads
+it later (Figure "The algorithm randUTV"; the small SVDs' sweep count is
+decided on the device).  Results are checked against the FP64 oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+E_UNSUPPORTED = -900
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_00998_amd import binding
+    binding.lib()
+    return binding
+
+
+def _case(wl, m, n, b, seed):
+    sig = np.exp(-np.arange(1, min(m, n) + 1) / (2.0 * b))
+    A = wl.planted(m, n, sig, seed=seed)
+    G = wl.gaussian_g(m, n, b, seed=seed + 1)
+    return A, G
+
+
+def test_two_factorizations_back_to_back(B):
+    """Two factorizations enqueued back to back on one stream with no host
+    wait in between, each with its own workspace; then the status of each."""
+    from oracle import randutv_ref as ref
+    from paper_1703_00998_amd import workloads as wl
+    cases = [(300, 200, 32, 1, 0), (257, 250, 48, 2, 10)]
+    runs = []
+    for (m, n, b, q, seed) in cases:
+        A, G = _case(wl, m, n, b, seed)
+        T, dG = B.colmajor(A), B.colmajor(G)
+        U, V = B.empty_colmajor(m, m), B.empty_colmajor(n, n)
+        work = B.workspace(B.workspace_size(m, n, b, q, "fp64", True, True))
+        assert B.randutv_factor(T, dG, b, q, U=U, V=V, work=work, sync=False) is None
+        runs.append((A, G, b, q, T, U, V, work, dG))
+    for (A, G, b, q, T, U, V, work, _) in runs:
+        st, k = B.randutv_status(work)
+        assert st == 0 and k == min(A.shape)
+        Uo, To, Vo, ko = ref.randutv(A, b, q, G)
+        assert ko == k
+        for got, want in ((T, To), (U, Uo), (V, Vo)):
+            np.testing.assert_allclose(got.cpu().numpy(), want, rtol=0, atol=1e-10)
+
+
+def test_enqueue_returns_before_the_device_finishes(B):
+    """A 4000 x 4000 factorization takes tens of milliseconds on the device;
+    right after the call returns, the stream still has work pending."""
+    from paper_1703_00998_amd import workloads as wl
+    m = n = 4000
+    b, q = 128, 1
+    A, G = _case(wl, m, n, b, 3)
+    dA, dG = B.colmajor(A), B.colmajor(G)
+    T = B.empty_colmajor(m, n)
+    U, V = B.empty_colmajor(m, m), B.empty_colmajor(n, n)
+    work = B.workspace(B.workspace_size(m, n, b, q, "fp64", True, True))
+    T.copy_(dA)
+    B.randutv_factor(T, dG, b, q, U=U, V=V, work=work, sync=False)  # warm-up
+    B.randutv_status(work)
+    T.copy_(dA)
+    torch.cuda.synchronize()
+    B.randutv_factor(T, dG, b, q, U=U, V=V, work=work, sync=False)
+    pending = not torch.cuda.current_stream().query()
+    st, k = B.randutv_status(work)
+    assert pending
+    assert st == 0 and k == n
+    res = torch.linalg.norm(dA - U @ (T @ V.T)).item() / torch.linalg.norm(dA).item()
+    assert res < 1e-13
+
+
+def test_status_of_early_stop_and_rsvd(B):
+    from paper_1703_00998_amd import workloads as wl
+    m, n, b = 400, 300, 32
+    A, G = _case(wl, m, n, b, 5)
+    T, dG = B.colmajor(A), B.colmajor(G)
+    work = B.workspace(B.workspace_size(m, n, b, 1, "fp64", False, False))
+    B.randutv_factor(T, dG, b, 1, k_stop=70, work=work, sync=False)
+    assert B.randutv_status(work) == (0, 96)
+    dA = B.colmajor(A)
+    Gr = B.colmajor(np.random.default_rng(1).standard_normal((m, 40)))
+    rwork = B.workspace(1 << 26)
+    B.randutv_rsvd(dA, Gr, 40, 1, prec="fp64", work=rwork, sync=False)
+    assert B.randutv_status(rwork) == (0, 40)
+
+
+def test_status_of_an_unused_workspace(B):
+    work = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+    st, _ = B.randutv_status(work, raise_on_error=False)
+    assert st == E_UNSUPPORTED

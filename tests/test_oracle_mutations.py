@@ -2,7 +2,8 @@
 into a copy of the oracle's source (a flipped Householder sign, a wrong row
 range, a dropped power iteration, a reused Gaussian slab, a transposed
 rotation, a wrong tau, a flipped canonical sign, an early-stop off by one,
-and mistakes in the RSVD and lower-triangular functions), runs the pins of
+mistakes in the RSVD and lower-triangular functions, and in the U / V flop
+count), runs the pins of
 tests/test_oracle_pins.py against the copy, and requires that several of
 them fail.  CPU only; the real oracle is untouched.
 
@@ -38,6 +39,9 @@ MUTATIONS = [
     ("early stop off by one", "c1 >= k_stop", "c1 > k_stop"),
     ("rsvd basis truncated early", "Q @ W[:, :k], Q", "Q[:, :k] @ W[:k, :k], Q"),
     ("lower form swaps U and V", "return V1, T1.T.copy(), U1, k", "return U1, T1.T.copy(), V1, k"),
+    ("U/V flop count sign of 2mn^2", "- 2.0 * m * n * n + 2.0 * n ** 3",
+     "+ 2.0 * m * n * n + 2.0 * n ** 3"),
+    ("U/V flop count drops 2n^3", "- 2.0 * m * n * n + 2.0 * n ** 3", "- 2.0 * m * n * n"),
 ]
 
 

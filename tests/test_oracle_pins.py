@@ -455,6 +455,47 @@ def test_flop_formula_golden_ratios():
         assert abs(exact / ref.flops_paper(m, n, q) - 1) < 0.05
 
 
+def _uv_forward_flops(m, n, b):
+    """Flops of forming U and V by forward accumulation, summed step by step
+    over the partitions of Figure randUTV (m >= n): each step applies its
+    block of w = |J2| reflectors, which act on rows I2 u I3 (m_i of them) of
+    U's trailing columns and rows J2 u J3 (n_i) of V's, to all m rows of U
+    and n rows of V (U(:,[I2,I3]) and V(:,[J2,J3]) times the orthogonal
+    factor): two thin products each in the compact WY form, 4 m m_i w + 2 m
+    w^2 and 4 n n_i w + 2 n w^2; then the small-SVD rotations of the step,
+    U(:,I2) Us and V(:,J2) Vs, 2 m w^2 + 2 n w^2.  The last step (no
+    randomization) applies the QR reflectors of its tall block to U only
+    (its square case has none), then its rotations."""
+    tot = 0.0
+    for i in range(ref.num_steps(m, n, b)):
+        r0 = i * b
+        w = min(r0 + b, n) - r0
+        mi, ni = m - r0, n - r0
+        if r0 + b < m and r0 + b < n:
+            tot += 4 * m * mi * w + 2 * m * w * w + 4 * n * ni * w + 2 * n * w * w
+            tot += 2 * m * w * w + 2 * n * w * w
+        else:
+            c = ni
+            if mi > c:
+                tot += 4 * m * mi * c + 2 * m * c * c
+            tot += 2 * m * c * c + 2 * n * c * c
+    return tot
+
+
+@pytest.mark.parametrize("m,n", [(8000, 8000), (4000, 4000), (20000, 5000), (6000, 2000)])
+def test_flops_uv_is_leading_order_of_per_step_sum(m, n):
+    """flops_uv (4 m^2 n - 2 m n^2 + 2 n^3, the U and V formation of Figure
+    randUTV by forward accumulation) is the leading-order term of the exact
+    per-step sum: with a tiny block size (b = 4) the two agree to well under
+    1 %, and at the workloads' block sizes they differ by the O(b/n) terms
+    the formula drops (below 3 b / n relatively)."""
+    exact = _uv_forward_flops(m, n, 4)
+    assert abs(ref.flops_uv(m, n) / exact - 1.0) < 0.005
+    for b in (128, 256):
+        exact = _uv_forward_flops(m, n, b)
+        assert 0.0 < 1.0 - ref.flops_uv(m, n) / exact < 3.0 * b / n
+
+
 def test_approx_equals_truncated_factor():
     """eq. Ak_randUTV and Theorem (b): A_k = U(:,1:k) T(1:k,:) V^T = U_k U_k^T A,
     and it does not depend on the small SVD rotations (skipped in approx)."""
