@@ -161,6 +161,29 @@ int randutv_factor(int64_t m, int64_t n, int64_t b, int q,
 int randutv_status(const void* work, size_t work_bytes, int64_t* k_out, void* stream);
 
 /*
+ * randutv_factor_noalloc -- randutv_factor for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments 1..11 as randutv_factor;
+ * no workspace argument: the workspace is a 128 MiB device array of the
+ * library, one per GPU, held until the process ends.  The call allocates
+ * nothing (no hipMalloc, hipFree, stream or event creation); U and V are
+ * updated on `stream` itself.  Sizes whose randutv_workspace_size exceeds
+ * 128 MiB (for example 4000 x 4000 with b = 256; 4000 x 4000 with b = 128
+ * fits) return RANDUTV_E_WORKSPACE before any work is enqueued.  All calls
+ * on one GPU share its array: calls that overlap in time on one GPU (on
+ * different streams or host threads) race; calls on one stream do not.
+ * Status through k_out as for randutv_factor (12 k_out, 13 stream).
+ */
+int randutv_factor_noalloc(int64_t m, int64_t n, int64_t b, int q,
+                           double* T, int64_t ldt,
+                           const double* G, int64_t ldg,
+                           double* U, int64_t ldu,
+                           double* V, int64_t ldv,
+                           int64_t k_stop, double tol,
+                           int prec, unsigned flags,
+                           int64_t* k_out, void* stream);
+
+/*
  * randutv_factor_lower -- the same factorization with a lower-triangular
  * middle factor, A = U L V^T (Section 1: the middle factor may be taken
  * upper or lower triangular).  Computed as randutv_factor of A^T

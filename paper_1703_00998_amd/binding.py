@@ -103,6 +103,9 @@ def lib():
     L.randutv_approx_backward.argtypes = [i64, i64, i64, i32, i64, vp, i64, vp, i64, vp, i64, vp,
                                           sz, vp, i64, vp, i64, i32, vp, sz, vp]
     L.randutv_approx_backward.restype = i32
+    L.randutv_factor_noalloc.argtypes = [i64, i64, i64, i32, vp, i64, vp, i64, vp, i64, vp, i64,
+                                         i64, dbl, i32, u32, ctypes.POINTER(i64), vp]
+    L.randutv_factor_noalloc.restype = i32
     L.randutv_status.argtypes = [vp, sz, ctypes.POINTER(i64), vp]
     L.randutv_status.restype = i32
     L.randutv_strerror.argtypes = [i32]
@@ -116,7 +119,7 @@ EXPORTS = ["randutv_random_steps", "randutv_g_cols", "randutv_workspace_size",
            "randutv_workspace_size_lower", "randutv_factor_lower", "randutv_rsvd_workspace_size", "randutv_rsvd", "randutv_gemm",
            "randutv_panel_work_size", "randutv_panel_qr",
            "randutv_small_svd_work_size", "randutv_small_svd", "randutv_strerror",
-           "randutv_status",
+           "randutv_status", "randutv_factor_noalloc",
            "randutv_profile_begin", "randutv_profile_begin_class", "randutv_profile_end", "randutv_profile_class_name",
            "randutv_approx_tape_size", "randutv_approx_work_size", "randutv_approx",
            "randutv_approx_backward_work_size", "randutv_approx_backward"]
@@ -258,6 +261,28 @@ def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", w
             m, n, b, q, _ptr(T), ldt, gp, ldg, _ptr(U), ldu, _ptr(V), ldv, int(k_stop),
             float(tol), PREC[prec], flags, wp, wbytes, kp, _stream())
         _check(st, "randutv_factor")
+    return int(k.value) if (sync or tol > 0) else None
+
+
+def randutv_factor_noalloc(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64",
+                           sync=True):
+    """randutv_factor on the library's own device workspace (no allocation by
+    the call).  Returns k when sync=True, else None."""
+    m, n = T.shape
+    ldt = _ld(T, m)
+    gc = g_cols(m, n, b)
+    ldg = _ld(G, m) if (G is not None and G.numel() > 0) else max(m, 1)
+    if gc > 0 and (G is None or G.shape[1] < gc):
+        raise RandUTVError(f"G needs {gc} columns")
+    ldu = _ld(U, m) if U is not None else m
+    ldv = _ld(V, n) if V is not None else n
+    flags = (FORM_U if U is not None else 0) | (FORM_V if V is not None else 0)
+    k = ctypes.c_int64(0)
+    kp = ctypes.byref(k) if (sync or tol > 0) else None
+    st = lib().randutv_factor_noalloc(
+        m, n, b, q, _ptr(T), ldt, _ptr(G) if gc > 0 else ctypes.c_void_p(0), ldg, _ptr(U), ldu,
+        _ptr(V), ldv, int(k_stop), float(tol), PREC[prec], flags, kp, _stream())
+    _check(st, "randutv_factor_noalloc")
     return int(k.value) if (sync or tol > 0) else None
 
 

@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librandutv.so")
-SOURCES = ["gemm.hip", "panel.hip", "panel_hr.hip", "svd.hip", "aux.hip", "prof.hip", "randutv.hip", "approx.hip", "rsvd.hip"]
+SOURCES = ["gemm.hip", "panel.hip", "panel_hr.hip", "svd.hip", "aux.hip", "prof.hip", "randutv.hip",
+           "approx.hip", "rsvd.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

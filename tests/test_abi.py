@@ -99,6 +99,30 @@ def test_workspace_and_argument_validation(lib):
     assert lib.randutv_strerror(-900) == b"unsupported case"
 
 
+def test_noalloc_entry_point_validates(lib):
+    """randutv_factor_noalloc checks its arguments, and the size limit of its
+    static workspace, before it touches the device."""
+    vp = ctypes.c_void_p
+    null = vp(0)
+    fake = vp(1 << 20)
+
+    def call(m=100, n=80, b=16, q=1, T=fake, ldt=100, G=fake, U=null, V=null, prec=0, flags=0):
+        return lib.randutv_factor_noalloc(m, n, b, q, T, ldt, G, m, U, m, V, n, 0, 0.0, prec,
+                                          flags, None, null)
+    assert call(m=0) == -1
+    assert call(b=0) == -2
+    assert call(q=-1) == -3
+    assert call(T=null) == -4
+    assert call(ldt=50) == -4
+    assert call(G=null) == -5
+    assert call(flags=1) == -6
+    assert call(flags=2) == -7
+    assert call(prec=5) == -10
+    assert call(flags=8) == -11
+    # 4000 x 4000, b = 256 with U and V needs more than the 128 MiB array.
+    assert call(m=4000, n=4000, b=256, ldt=4000, U=fake, V=fake, flags=3) == -901
+
+
 def test_oversampled_entry_points_validate(lib):
     sz = ctypes.c_size_t(0)
     sz0 = ctypes.c_size_t(0)
