@@ -265,9 +265,24 @@ def early_stop_run(B, torch, wl):
         k = res["k"]
         tail = torch.linalg.norm(T[k:, k:]).item() / nA
         log(f"early stop: k={k}, {ms:.2f} ms, ||A-A_k||/||A|| = {tail:.3e}")
+        # The same with the economy U (20000 x 5000) and V formed.
+        U = B.empty_colmajor(m, n)
+        V = B.empty_colmajor(n, n)
+        work2 = B.workspace(B.workspace_size(m, n, b, q, "fp64", True, True, econ_u=True))
+
+        def step_uv():
+            T.copy_(dA)
+            res["k"] = B.randutv_factor(T, dG, b, q, U=U, V=V, tol=1e-6, work=work2)
+
+        ms_uv = _timed(torch, step_uv, 3)
+        k2 = res["k"]
+        err = torch.linalg.norm(dA - U[:, :k2] @ (T[:k2] @ V.T)).item() / nA
+        log(f"early stop, economy U and V: k={k2}, {ms_uv:.2f} ms, ||A-U_k T_k V^T||/||A|| = {err:.3e}")
         return {"ms": ms, "k": k, "rel_err": tail,
                 "config": "20000x5000 rank-300 (sigma_j=1/j) + noise 1e-8||A||, b=128, q=2, "
-                          "tol=1e-6, FP64, U,V not formed"}
+                          "tol=1e-6, FP64, U,V not formed",
+                "econ_u_v_formed": {"ms": ms_uv, "k": k2, "rel_err": err,
+                                    "config": "the same with U (20000x5000, economy) and V formed"}}
     except Exception as e:  # reported, never fatal to the headline line
         return {"error": repr(e)}
 

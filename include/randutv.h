@@ -67,7 +67,8 @@ typedef enum {
 /* Flags of randutv_factor. */
 enum {
   RANDUTV_FORM_U = 1, /* accumulate U (m x m) */
-  RANDUTV_FORM_V = 2  /* accumulate V (n x n) */
+  RANDUTV_FORM_V = 2, /* accumulate V (n x n) */
+  RANDUTV_ECON_U = 4  /* with FORM_U: only U's first min(m, n) columns (m x min(m, n)) */
 };
 
 /* Number of randomized steps of Figure "The algorithm randUTV": steps i
@@ -105,8 +106,12 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
  *              m - i*b rows of column block i (the paper draws a fresh
  *              m - b(i-1) by b Gaussian matrix each step).  ldg >= m.  May be NULL only
  *              if randutv_g_cols() == 0.
- *  6  U, ldu   out (if flags & RANDUTV_FORM_U): m x m orthogonal U.  Else may
- *              be NULL.  ldu >= m.
+ *  6  U, ldu   out (if flags & RANDUTV_FORM_U): m x m orthogonal U, or with
+ *              RANDUTV_ECON_U its first min(m, n) columns (m x min(m, n),
+ *              orthonormal): A = U T(0:min(m,n), :) V^T after a full
+ *              factorization, and U(:, 0:k) is the left factor of the rank-k
+ *              approximation after an early stop at k (Section 1.1, advantage
+ *              (ii): O(mnk) storage).  Else may be NULL.  ldu >= m.
  *  7  V, ldv   out (if flags & RANDUTV_FORM_V): n x n orthogonal V.  Else may
  *              be NULL.  ldv >= n.
  *  8  k_stop   > 0: stop after the first step whose column count reaches
@@ -115,7 +120,10 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
  *              tol * ||A||_F (Section 1.1, advantage (ii)); this makes the
  *              call wait on the stream once per step.  <= 0: no test.
  * 10  prec     randutv_prec.
- * 11  flags    RANDUTV_FORM_U | RANDUTV_FORM_V.
+ * 11  flags    RANDUTV_FORM_U | RANDUTV_FORM_V, and RANDUTV_ECON_U with
+ *              FORM_U (the economy U is formed after the loop, from the left
+ *              reflectors kept in its own columns, by backward accumulation;
+ *              the full U by forward accumulation on a second stream).
  * 12  work     device workspace of at least randutv_workspace_size() bytes,
  *              256-byte aligned.  Contents on entry are ignored.
  * 13  work_bytes
@@ -197,6 +205,7 @@ int randutv_factor_noalloc(int64_t m, int64_t n, int64_t b, int q,
  *  5  G, ldg   packed N(0,1) matrix of the n x m problem:
  *              n x randutv_g_cols(n, m, b), ldg >= n.
  * 12  work     randutv_workspace_size_lower() bytes.
+ * 11  flags    RANDUTV_FORM_U | RANDUTV_FORM_V (no economy form).
  * Statuses as randutv_factor (argument numbers of this call), except that
  * a HIP or numerical status from the inner factorization is passed on.
  */

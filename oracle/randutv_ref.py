@@ -175,7 +175,7 @@ def top_left_singular_vectors(Y, b):
 # --------------------------------------------------------------------------
 def randutv(A, b, q, G, *, p=0, form_u=True, form_v=True, k_stop=0, tol=0.0,
             small_svds=True):
-    """[U, T, V, k] = randUTV(A, b, q) following Figure randUTV step by step.
+    """The blocked randUTV of Section 5.2 (Figure randUTV): A = U T V^T.
 
     A: m x n (any shape).  G: m x (num_random_steps*(b+p)) packed Gaussian.
     p > 0 over-samples (Remark "Oversampling" in Section 5.3, Appendix A.2,

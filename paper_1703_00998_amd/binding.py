@@ -23,7 +23,7 @@ PREC = {"fp64": RANDUTV_FP64, "fp32": RANDUTV_FP32, "bf16x3": RANDUTV_BF16X3,
         "bf16x3_fp32": RANDUTV_BF16X3_FP32, "bf16x3_bf16x6": RANDUTV_BF16X3_BF16X6}
 # Arithmetic codes of randutv_gemm (a product has one arithmetic).
 GEMM_PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 4}
-FORM_U, FORM_V = 1, 2
+FORM_U, FORM_V, ECON_U = 1, 2, 4
 
 _lib = None
 
@@ -202,8 +202,8 @@ def g_cols(m, n, b, p=0):
     return int(lib().randutv_g_cols(m, n, b))
 
 
-def workspace_size(m, n, b, q=1, prec="fp64", form_u=True, form_v=True, p=0):
-    flags = (FORM_U if form_u else 0) | (FORM_V if form_v else 0)
+def workspace_size(m, n, b, q=1, prec="fp64", form_u=True, form_v=True, p=0, econ_u=False):
+    flags = (FORM_U if form_u else 0) | (FORM_V if form_v else 0) | (ECON_U if econ_u else 0)
     out = ctypes.c_size_t(0)
     if p:
         _check(lib().randutv_workspace_size_p(m, n, b, p, q, PREC[prec], flags,
@@ -228,7 +228,8 @@ def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", w
                    sync=True, p=0):
     """In-place randUTV of T (m x n column-major FP64, overwritten by T).
 
-    U (m x m) and V (n x n) are written when given.  p > 0 over-samples
+    U (m x m, or m x min(m, n) for the economy form) and V (n x n) are
+    written when given.  p > 0 over-samples
     (randutv_factor_p; G then has b + p columns per randomized step).
     Returns k (the number of leading columns reduced) when sync=True, else
     None (enqueue only).
@@ -241,8 +242,12 @@ def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", w
         raise RandUTVError(f"G needs {gc} columns")
     ldu = _ld(U, m) if U is not None else m
     ldv = _ld(V, n) if V is not None else n
-    flags = (FORM_U if U is not None else 0) | (FORM_V if V is not None else 0)
-    need = workspace_size(m, n, b, q, prec, U is not None, V is not None, p=p)
+    econ = U is not None and U.shape[1] == min(m, n) and min(m, n) < m
+    if U is not None and U.shape[1] not in (m, min(m, n)):
+        raise RandUTVError("U must have m or min(m, n) columns")
+    flags = (FORM_U if U is not None else 0) | (FORM_V if V is not None else 0) | \
+        (ECON_U if econ else 0)
+    need = workspace_size(m, n, b, q, prec, U is not None, V is not None, p=p, econ_u=econ)
     if work is None:
         work = workspace(need, T.device)
     wp, wbytes = _aligned_ptr(work)

@@ -67,6 +67,11 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc,
                 double* splitws, size_t splitws_elems, bool small_tiles = false);
+// +1 / -1 around the products of a panel factorization: the FP64 products
+// in between launch their own kernel instantiation (same code), so traces
+// and counters tell them from the method's thin products.  Host-side, one
+// enqueuing thread at a time (as the factorization's lock ensures).
+void gemm_panel_scope(int delta);
 
 // ---------------------------------------------------------------- panel QR
 struct PanelWork {

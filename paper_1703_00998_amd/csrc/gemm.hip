@@ -23,6 +23,9 @@ namespace rutv {
 namespace {
 
 constexpr int PAD = 2;
+#ifndef K64_SLAB
+#define K64_SLAB 16
+#endif
 constexpr int kSmallMN = 128;  // products at most this size in M and N
 constexpr int kSmallK = 512;   // and this deep go to k_gemm_small (FP64)
 
@@ -39,24 +42,13 @@ __device__ inline v4f mfmabf(v8bf a, v8bf b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-template <int P>
-struct Cfg;
-template <>
-struct Cfg<PREC_FP64> {
-  static constexpr int BK = 16;
-};
-template <>
-struct Cfg<PREC_FP32> {
-  static constexpr int BK = 16;
-};
-template <>
-struct Cfg<PREC_BF16X3> {
-  static constexpr int BK = 32;
-};
-template <>
-struct Cfg<PREC_BF16X6> {
-  static constexpr int BK = 32;
-};
+// K depth of one LDS slab: 16 for the FP64 and FP32 MFMAs (16x16x4), 32 for
+// the BF16 ones (16x16x32).  32-deep slabs on the 64 x 64 FP64 tiles (67 KB
+// of LDS per workgroup) made the 8000 x 8000 factorization 8-10 ms slower.
+template <int P, int BM>
+constexpr int slab_k() {
+  return (P == PREC_BF16X3 || P == PREC_BF16X6) ? 32 : (BM <= 64 ? K64_SLAB : 16);
+}
 
 // LDS slabs of one K step, per arithmetic.  FP64/FP32: [k][i] with i
 // contiguous (MFMA 16x16x4 takes one element per lane).  BF16 pieces:
@@ -69,13 +61,13 @@ template <int P, int BM, int BN>
 struct Slabs;
 template <int BM, int BN>
 struct Slabs<PREC_FP64, BM, BN> {
-  double A[2][16][BM + PAD];
-  double B[2][16][BN + PAD];
+  double A[2][slab_k<PREC_FP64, BM>()][BM + PAD];
+  double B[2][slab_k<PREC_FP64, BM>()][BN + PAD];
 };
 template <int BM, int BN>
 struct Slabs<PREC_FP32, BM, BN> {
-  float A[2][16][BM + PAD];
-  float B[2][16][BN + PAD];
+  float A[2][slab_k<PREC_FP32, BM>()][BM + PAD];
+  float B[2][slab_k<PREC_FP32, BM>()][BN + PAD];
 };
 template <int BM, int BN>
 struct Slabs<PREC_BF16X3, BM, BN> {
@@ -118,13 +110,17 @@ __device__ inline Bf3 split3(float x32) {
 // 128 x 128 tiles at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26 without
 // it).  Operands are FP64 in memory for every arithmetic; the loader
 // converts.
-template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN>
+// ROLE tells apart two instantiations of the same code: 0 for the method's
+// thin products (sampling, trailing updates, U and V, fold-back), 1 for the
+// products inside the Householder panel factorizations, so that kernel
+// traces and counters attribute them separately.
+template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN, int ROLE>
 __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
     int M, int N, int K, int kper, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double* __restrict__ C, int64_t ldc,
     int64_t zstride, double alpha, double beta) {
   constexpr int NT = 64 * WM * WN;                     // threads
-  constexpr int BK = Cfg<P>::BK;
+  constexpr int BK = slab_k<P, BM>();
   constexpr int PM = BM / WM, PN = BN / WN;            // per-wave part
   constexpr int FM = PM / 16, FN = PN / 16;            // MFMA blocks per wave
   constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // elements per thread
@@ -331,23 +327,61 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
   // leave D(row = 4(lane>>4) + r, col = lane&15).  So C(row, col) with
   // row = m0 + wm*BM/2 + x*16 + (lane&15) and col = n0 + wn*BN/2 + y*16 +
   // ((lane>>4) + 4r) for FP64, (4(lane>>4) + r) otherwise.
+  // With beta != 0 the old values of one 16-row block (FN * 4 per lane) are
+  // all loaded before any of them is written: loads and stores of C may
+  // alias as far as the compiler knows, so element-by-element code waits for
+  // each load in turn (64 round trips per lane on a 128 x 128 tile).  Tiles
+  // inside C take a path without per-element guards, whose stores then need
+  // no waits between them.
+  auto colof = [&](int y, int r) {
+    return n0 + wn * PN + y * 16 + (P == PREC_FP64 ? kr + 4 * r : 4 * kr + r);
+  };
+  if (m0 + BM <= M && n0 + BN <= N) {
+#pragma unroll
+    for (int x = 0; x < FM; ++x) {
+      double* Cr = C + (m0 + wm * PM + x * 16 + cr);
+      double old[FN][4];
+      if (beta != 0.0) {
+#pragma unroll
+        for (int y = 0; y < FN; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) old[y][r] = Cr[(int64_t)colof(y, r) * ldc];
+      }
+#pragma unroll
+      for (int y = 0; y < FN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double v = alpha * (double)acc[x][y][r];
+          Cr[(int64_t)colof(y, r) * ldc] = beta != 0.0 ? v + beta * old[y][r] : v;
+        }
+    }
+    return;
+  }
 #pragma unroll
   for (int x = 0; x < FM; ++x) {
     const int row = m0 + wm * PM + x * 16 + cr;
-    if (row >= M) continue;
+    const bool rok = row < M;
+    double old[FN][4];
+    if (beta != 0.0) {
 #pragma unroll
-    for (int y = 0; y < FN; ++y) {
+      for (int y = 0; y < FN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = colof(y, r);
+          old[y][r] = (rok && col < N) ? C[row + (int64_t)col * ldc] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int y = 0; y < FN; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int col = n0 + wn * PN + y * 16 + (P == PREC_FP64 ? kr + 4 * r : 4 * kr + r);
-        if (col < N) {
-          double* p = C + row + (int64_t)col * ldc;
+        const int col = colof(y, r);
+        if (rok && col < N) {
           double v = alpha * (double)acc[x][y][r];
-          if (beta != 0.0) v += beta * *p;
-          *p = v;
+          if (beta != 0.0) v += beta * old[y][r];
+          C[row + (int64_t)col * ldc] = v;
         }
       }
-    }
   }
 }
 
@@ -392,15 +426,18 @@ __global__ __launch_bounds__(64) void k_gemm_small(int M, int N, int K, const do
   }
   const int row = m0 + li;
   if (row >= M) return;
+  double old[4] = {0.0, 0.0, 0.0, 0.0};  // loaded together, before any store
+  if (beta != 0.0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int col = n0 + lk + 4 * r;
+      if (col < N) old[r] = C[row + (int64_t)col * ldc];
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int col = n0 + lk + 4 * r;
-    if (col < N) {
-      double* p = C + row + (int64_t)col * ldc;
-      double v = alpha * (acc0[r] + acc1[r]);
-      if (beta != 0.0) v += beta * *p;
-      *p = v;
-    }
+    if (col < N) C[row + (int64_t)col * ldc] = alpha * (acc0[r] + acc1[r]) + beta * old[r];
   }
 }
 
@@ -431,34 +468,38 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ 
   }
 }
 
-template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN>
+template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN, int ROLE>
 void launch(hipStream_t st, dim3 grid, int M, int N, int K, int kper, const double* A,
             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
             int64_t zstride, double alpha, double beta) {
-  hipLaunchKernelGGL((k_gemm<P, TA, TB, BM, BN, WM, WN>), grid, dim3(64 * WM * WN), 0, st, M, N, K,
+  hipLaunchKernelGGL((k_gemm<P, TA, TB, BM, BN, WM, WN, ROLE>), grid, dim3(64 * WM * WN), 0, st, M, N, K,
                      kper, A, lda, B, ldb, C, ldc, zstride, alpha, beta);
 }
 
-template <int P, int BM, int BN, int WM, int WN>
+template <int P, int BM, int BN, int WM, int WN, int ROLE>
 void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, int kper,
               const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
               int64_t ldc, int64_t zs, double al, double be) {
-  if (!ta && !tb) launch<P, false, false, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (ta && !tb) launch<P, true, false, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (!ta && tb) launch<P, false, true, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else launch<P, true, true, BM, BN, WM, WN>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  if (!ta && !tb) launch<P, false, false, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (ta && !tb) launch<P, true, false, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (!ta && tb) launch<P, false, true, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else launch<P, true, true, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
 // Tile shapes: 0 = 64 x 64, 1 = 128 x 128, both on 2 x 2 waves.
-template <int P>
+template <int P, int ROLE = 0>
 void launch_p(hipStream_t st, int shape, bool ta, bool tb, dim3 grid, int M, int N, int K,
               int kper, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
               int64_t ldc, int64_t zs, double al, double be) {
-  if (shape == 1) launch_t<P, 128, 128, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else launch_t<P, 64, 64, 2, 2>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  if (shape == 1) launch_t<P, 128, 128, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else launch_t<P, 64, 64, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
+int g_panel_scope = 0;  // > 0 while a panel factorization enqueues its products
+
 }  // namespace
+
+void gemm_panel_scope(int delta) { g_panel_scope += delta; }
 
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
@@ -476,7 +517,6 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
               8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)));
     return hipGetLastError();
   }
-  const int BK = (prec == PREC_BF16X3 || prec == PREC_BF16X6) ? 32 : 16;
   // 128 x 128 tiles when the output, or the output times a split of K,
   // gives enough workgroups; else 64 x 64.  Long reductions are split over
   // blockIdx.z until about two workgroups per CU are in flight.
@@ -487,6 +527,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   // measured slower than two 128 x 128 workgroups per CU on every thin
   // product of the step, in all three arithmetics.)
   const int shape = big ? 1 : 0;
+  // Slab depth of the chosen tile (split-K boundaries are multiples of it).
+  const int BK = (prec == PREC_BF16X3 || prec == PREC_BF16X6) ? 32 : (shape ? 16 : K64_SLAB);
   const int BMs = shape ? 128 : 64, BNs = shape ? 128 : 64;
   const int tm = (M + BMs - 1) / BMs, tn = (N + BNs - 1) / BNs;
   const int tiles = tm * tn;
@@ -533,6 +575,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     launch_p<PREC_BF16X6>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else if (prec == PREC_BF16X3)
     launch_p<PREC_BF16X3>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else if (g_panel_scope > 0)
+    launch_p<PREC_FP64, 1>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else
     launch_p<PREC_FP64>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   prof_done(st, slot, cls, 2.0 * M * N * (double)K,

@@ -331,37 +331,16 @@ __device__ inline double ld_coh(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier for the LDS-resident kernel.  All data exchanged across
-// workgroups in that kernel is written and read with device-coherent
-// (agent-scope atomic, sc1) accesses, so no L2 writeback or invalidation is
-// needed: each wave waits until its own coherent stores are acknowledged
-// (vmcnt = 0) before the workgroup arrives, and data is read only after the
-// generation change is observed.
-__device__ inline void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
-
-__device__ void grid_sync_coh(unsigned* bar, unsigned nwg, int* err) {
-  wait_stores();
-  __syncthreads();
-  if (threadIdx.x == 0 && nwg > 1) {
-    const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (a == nwg - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      wait_stores();
-      __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned it = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-        if (++it > kSpinLimit) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-  }
-  __syncthreads();
+// Grid barrier for the LDS-resident kernel.  Data exchanged across its
+// workgroups is written and read with device-coherent (agent-scope atomic)
+// accesses; the barrier itself is the release / acquire one above (an
+// agent-scope release fence in every thread before arriving, the arrival as
+// an acquire-release atomic, the generation published with release, and an
+// agent-scope acquire fence in every thread after it is observed), so the
+// exchange is ordered by the HIP memory model rather than by waiting for
+// store acknowledgements.  Bounded like grid_sync.
+__device__ inline void grid_sync_coh(unsigned* bar, unsigned nwg, int* err) {
+  grid_sync(bar, nwg, err);
 }
 
 // LDS besides the slab: sred, sTs, stau, srowTw, sg/srow/sw/shh, the

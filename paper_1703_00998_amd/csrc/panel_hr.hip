@@ -996,12 +996,14 @@ hipError_t panel_qr_hr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, d
   if (nb > 2 * kBlk || Mp < nb) return hipErrorInvalidValue;
   const int slot = prof_mark(st, PC_PANEL);
   prof_suppress(1);
+  gemm_panel_scope(1);
   hipError_t e = hr_panel(st, Mp, nb, P, ldp, V, ldv, Rout, ldr, tau, Tw, ldtw, hw, split,
                           split_elems);
   // Fallback, gated on the flag: column-by-column Householder of the
   // (untouched) panel, then its V and R.
   if (e == hipSuccess) e = panel_qr(st, Mp, nb, P, ldp, tau, Tw, ldtw, pw, hw.flag);
   if (e == hipSuccess) e = panel_extract(st, Mp, nb, P, ldp, V, ldv, Rout, ldr, hw.flag);
+  gemm_panel_scope(-1);
   prof_suppress(-1);
   prof_done(st, slot, PC_PANEL, 2.0 * Mp * (double)nb * nb, 16.0 * Mp * (double)nb);
   return e == hipSuccess ? hipGetLastError() : e;

@@ -42,7 +42,7 @@ constexpr int kJacobiSweeps = 40;
 
 struct Layout {
   size_t status, Y, Vh, Vh2, Vh3, Z, Uh, Uh2, Uh3, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwV3, TwU, TwU2,
-      TwU3, tauV, tauU, Rst,
+      TwU3, tauV, tauU, Rst, TwUst,
       Ust, Vst, D, Jw, Jv, Ftmp, split, nrm, ints, panel, hr, total;
   // Over-sampling (p > 0) only: QR and SVD of the extended sample.
   size_t VY, TwY, RY, UR, VR, JwR, JvR, tauY, DR, Cy, Cy2, intsY;
@@ -54,6 +54,12 @@ struct Layout {
 constexpr int kIntsY = 2 + kJacobiSweeps;
 
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// FORM_U, FORM_V, and ECON_U together with FORM_U.
+bool valid_flags(unsigned flags) {
+  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V | RANDUTV_ECON_U)) return false;
+  return !(flags & RANDUTV_ECON_U) || (flags & RANDUTV_FORM_U);
+}
 
 int64_t num_steps(int64_t m, int64_t n, int64_t b) {
   return std::min((m + b - 1) / b, (n + b - 1) / b);
@@ -96,6 +102,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   L.tauV = take(b * d);
   L.tauU = take(b * d);
   L.Rst = take(s * bb * d);
+  L.TwUst = take(s * bb * d);  // compact-WY factors of the left transforms (economy U)
   L.Ust = take(s * bb * d);
   L.Vst = take(s * bb * d);
   L.D = take(s * b * d);
@@ -350,13 +357,14 @@ int randutv_workspace_size_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, 
   if (p < 0 || b + p > kMaxB) return -4;
   if (q < 0 || q > 16) return -5;
   if (prec < 0 || prec > kPrecMax) return -6;
-  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -7;
+  if (!valid_flags(flags)) return -7;
   if (!bytes) return -8;
   *bytes = make_layout(m, n, b, p).total;
   return 0;
 }
 
 // flags of the transposed problem: U of A^T is V of A and vice versa.
+// (The economy U has no counterpart for V, so the lower form takes neither.)
 inline unsigned swap_uv(unsigned flags) {
   return (flags & RANDUTV_FORM_U ? RANDUTV_FORM_V : 0u) | (flags & RANDUTV_FORM_V ? RANDUTV_FORM_U : 0u);
 }
@@ -379,7 +387,7 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, uns
   if (b < 1 || b > kMaxB) return -3;
   if (q < 0 || q > 16) return -4;
   if (prec < 0 || prec > kPrecMax) return -5;
-  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -6;
+  if (!valid_flags(flags)) return -6;
   if (!bytes) return -7;
   *bytes = make_layout(m, n, b).total;
   return 0;
@@ -484,7 +492,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   if (formU && (!U || ldu < m)) return -6;
   if (formV && (!V || ldv < n)) return -7;
   if (prec < 0 || prec > kPrecMax) return -10;
-  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -11;
+  if (!valid_flags(flags)) return -11;
   if (!work || ((uintptr_t)work & 255)) return -12;
   const Layout L = make_layout(m, n, b, p);
   if (work_bytes < L.total) return RANDUTV_E_WORKSPACE;
@@ -525,12 +533,21 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   double* const TwUS[kSlots] = {dp(L.TwU), dp(L.TwU2), dp(L.TwU3)};
   constexpr int kVR = 0, kUR = kSlots, kVD = 2 * kSlots, kUD = 3 * kSlots, kJoin = 4 * kSlots;
 
+  // Economy U (m x min(m, n)): each step's left reflectors are stored in U's
+  // own block column (rows r0..m, LAPACK's dgeqrf layout with explicit ones
+  // and zeros) and their compact-WY factors in a stash; U is formed after the
+  // loop by backward accumulation (Q [I; 0], last block first).
+  const bool econU = formU && (flags & RANDUTV_ECON_U);
+  const int cU = econU ? (int)std::min(m, n) : M;  // columns of U
+  double* TwUst = dp(L.TwUst);
+  int nrefl = 0;  // leading blocks whose left reflectors are stored in U
+
   HIPCHK(status_init(st, blk));
-  if (formU) HIPCHK(set_identity(st, M, M, U, ldu));
+  if (formU) HIPCHK(set_identity(st, M, cU, U, ldu));
   if (formV) HIPCHK(set_identity(st, N, N, V, ldv));
   // Without the second stream (use_side false) U and V are updated on the
   // caller's stream, in the same launches.
-  SideCtx* sc = (use_side && (formU || formV)) ? side_ctx() : nullptr;
+  SideCtx* sc = (use_side && ((formU && !econU) || formV)) ? side_ctx() : nullptr;
   const hipStream_t ss = sc ? sc->side : st;  // U / V stream (the main one if none)
   bool vpend[kSlots] = {}, upend[kSlots] = {};
   if (sc) {
@@ -571,6 +588,12 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     const int sl = (int)(i % kSlots);
     double *Vh = VhS[sl], *Uh = UhS[sl], *TwV = TwVS[sl], *TwU = TwUS[sl];
     double *RV = nullptr, *RU = Rst + (size_t)i * B * B;
+    int64_t ldUh = M;
+    if (econU) {  // left reflectors into U's block column, their factor to the stash
+      Uh = U + r0 + (int64_t)r0 * ldu;
+      ldUh = ldu;
+      TwU = TwUst + (size_t)i * B * B;
+    }
     if (tape) {  // reflectors and R factors of this step go to the tape
       Vh = tape->Vy(i);
       TwV = tape->Ty(i);
@@ -609,15 +632,16 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       // transform's reflectors and the diagonal block's R.
       // (The panel is read in place; T([I2,I3], J2) is overwritten below.)
       HIPCHK(reclaim(kUD + sl, upend[sl]));
-      HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, M, RU, B, tauU, TwU, B, hw, pw, split, se));
-      // T([I2,I3], J3) = Uq^T T([I2,I3], J3)
+      HIPCHK(panel_qr_hr(st, Mi, B, X, ldt, Uh, ldUh, RU, B, tauU, TwU, B, hw, pw, split, se));
+      if (econU) ++nrefl;
+      // Left transform of the trailing rows right of the block.
       const int Nr = Ni - B;
       double* XJ3 = X + (int64_t)B * ldt;
-      HIPCHK(gemm(st, pu, true, false, B, Nr, Mi, 1.0, Uh, M, XJ3, ldt, 0.0, C, B, split, se));
+      HIPCHK(gemm(st, pu, true, false, B, Nr, Mi, 1.0, Uh, ldUh, XJ3, ldt, 0.0, C, B, split, se));
       HIPCHK(gemm(st, PREC_FP64, true, false, B, Nr, B, 1.0, TwU, B, C, B, 0.0, C2, B, nullptr, 0));
-      HIPCHK(gemm(st, pu, false, false, Mi, Nr, B, -1.0, Uh, M, C2, B, 1.0, XJ3, ldt, nullptr, 0));
-      // U(:, [I2,I3]) = U(:, [I2,I3]) Uq
-      if (formU) {  // on the U / V stream
+      HIPCHK(gemm(st, pu, false, false, Mi, Nr, B, -1.0, Uh, ldUh, C2, B, 1.0, XJ3, ldt, nullptr, 0));
+      // U's trailing columns times the left transform (forward accumulation)
+      if (formU && !econU) {  // on the U / V stream
         double* UI = U + (int64_t)r0 * ldu;
         HIPCHK(to_side(kUR + sl));
         HIPCHK(gemm_side(ss, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, kSideChunk));
@@ -679,9 +703,10 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       // Last block: economic SVD via Householder QR of T([I2,I3],[J2,J3]).
       const int c = Ni;
       HIPCHK(reclaim(kUD + sl, upend[sl]));
-      HIPCHK(panel_qr_hr(st, Mi, c, X, ldt, Uh, M, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
+      HIPCHK(panel_qr_hr(st, Mi, c, X, ldt, Uh, ldUh, Rst + (size_t)i * B * B, B, tauU, TwU, B, hw,
                          pw, split, se));
-      if (formU) {
+      if (econU) ++nrefl;
+      if (formU && !econU) {
         double* UI = U + (int64_t)r0 * ldu;
         HIPCHK(to_side(kUR + sl));
         HIPCHK(gemm(ss, PREC_FP64, false, false, M, c, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, nullptr, 0));
@@ -713,6 +738,24 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   // while the U / V stream finishes its last products; U and V's part
   // waits for it.
   auto width = [&](int i) { return i == nsvd - 1 ? last_w : B; };
+  // Economy U by backward accumulation: for block i (last first), the
+  // columns right of it (already formed) times H_i = I - Uh_i Tw_i Uh_i^T,
+  // then the block's own columns H_i [I_w; 0] in place of its reflectors.
+  for (int i = nrefl - 1; i >= 0 && econU; --i) {
+    const int r0 = i * B, w = width(i), mi = M - r0, rest = cU - r0 - w;
+    const double* Uhi = U + r0 + (int64_t)r0 * ldu;
+    const double* Twi = TwUst + (size_t)i * B * B;
+    if (rest > 0) {
+      double* Xr = U + r0 + (int64_t)(r0 + w) * ldu;
+      HIPCHK(gemm(st, PREC_FP64, true, false, w, rest, mi, 1.0, Uhi, ldu, Xr, ldu, 0.0, C, w, split, se));
+      HIPCHK(gemm(st, PREC_FP64, false, false, w, rest, w, 1.0, Twi, B, C, w, 0.0, C2, w, nullptr, 0));
+      HIPCHK(gemm(st, PREC_FP64, false, false, mi, rest, w, -1.0, Uhi, ldu, C2, w, 1.0, Xr, ldu, nullptr, 0));
+    }
+    HIPCHK(gemm(st, PREC_FP64, false, true, w, w, w, 1.0, Twi, B, Uhi, ldu, 0.0, C2, w, nullptr, 0));
+    HIPCHK(set_identity(st, mi, w, Ftmp, mi));
+    HIPCHK(gemm(st, PREC_FP64, false, false, mi, w, w, -1.0, Uhi, ldu, C2, w, 1.0, Ftmp, mi, nullptr, 0));
+    HIPCHK(copy_matrix(st, mi, w, Ftmp, mi, U + r0 + (int64_t)r0 * ldu, ldu));
+  }
   hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(256), 0, st, nbs, nsvd, B, last_w);
   HIPCHK(batched_svd(st, nsvd, nbs, B, Rst, (int64_t)B * B, Ust, Vst, (int64_t)B * B, Dd, B, Jw, Jv,
                      jstatus, kJacobiSweeps, &blk->svd_fail));

@@ -67,6 +67,10 @@ def test_workspace_and_argument_validation(lib):
     assert lib.randutv_workspace_size(100, 80, 0, 1, 0, 3, ctypes.byref(sz)) == -3
     assert lib.randutv_workspace_size(100, 80, 16, -1, 0, 3, ctypes.byref(sz)) == -4
     assert lib.randutv_workspace_size(100, 80, 16, 1, 7, 3, ctypes.byref(sz)) == -5
+    # RANDUTV_ECON_U (4) only together with RANDUTV_FORM_U (1)
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 4, ctypes.byref(sz)) == -6
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 5, ctypes.byref(sz)) == 0
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 8, ctypes.byref(sz)) == -6
     vp = ctypes.c_void_p
     null = vp(0)
     fake = vp(1 << 20)  # never dereferenced: validation fails first
