@@ -599,6 +599,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the early-stop and differentiation workload timings")
+    ap.add_argument("--extra", default="q2,early_stop,approx,wide,oversample,rsvd,lower",
+                    help="which extra workloads to time (comma-separated)")
     ap.add_argument("--cpu-n", type=int, default=1024)
     ap.add_argument("--study", choices=["accuracy"],
                     help="instead of the timing line, run the rank-k accuracy study of "
@@ -705,19 +707,26 @@ def main():
                           "hardware": "Xeon E5-2695 v3 (Haswell), 14 cores, 2.3 GHz, "
                                       "MKL 11.2.3, FP64, b=64 (Tables 1 and 2)"},
     }
-    if not args.no_extra:
-        if q == 1:  # the same workload with q = 2 on the headline path
+    extra = set() if args.no_extra else {e for e in args.extra.split(",") if e}
+    if extra:
+        if q == 1 and "q2" in extra:  # the same workload with q = 2 on the headline path
             ms2, _, _, acc2, _ = run_path(B, torch, dA, dG, sig, m, n, b, 2, head, 3, 1)
             F2 = flops_total(m, n, 2)
             out["q2_8000"] = {"path": head, "ms": ms2, "tflops": F2 / (ms2 * 1e-3) / 1e12,
                               "residual": acc2["residual"],
                               "diag_rel_err_median": acc2["diag_rel_err_median"]}
-        out["early_stop_20000x5000"] = early_stop_run(B, torch, wl)
-        out["approx_2048x1024"] = approx_run(B, torch, wl)
-        out["wide_4000x8000"] = wide_run(B, torch, wl)
-        out["oversample_4000"] = oversample_run(B, torch, wl)
-        out["rsvd_8000"] = rsvd_run(B, torch, wl, dA, sig)
-        out["lower_8000"] = lower_run(B, torch, wl, dA)
+        if "early_stop" in extra:
+            out["early_stop_20000x5000"] = early_stop_run(B, torch, wl)
+        if "approx" in extra:
+            out["approx_2048x1024"] = approx_run(B, torch, wl)
+        if "wide" in extra:
+            out["wide_4000x8000"] = wide_run(B, torch, wl)
+        if "oversample" in extra:
+            out["oversample_4000"] = oversample_run(B, torch, wl)
+        if "rsvd" in extra:
+            out["rsvd_8000"] = rsvd_run(B, torch, wl, dA, sig)
+        if "lower" in extra:
+            out["lower_8000"] = lower_run(B, torch, wl, dA)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on a {args.cpu_n}x{args.cpu_n} sample ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, b, q)

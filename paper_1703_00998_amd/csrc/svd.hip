@@ -11,7 +11,12 @@
 // and V in LDS, and rotates every column pair across the two blocks once
 // (plus, in the first round of a sweep, the pairs inside each block), so a
 // sweep visits every column pair exactly once, as cyclic scalar Jacobi
-// does; waves take disjoint pairs.  Blocks stay in place in global memory, so
+// does.  Each 16-lane DPP row of a wave takes one pair of a sub-round (four
+// pairs per wave, the kBW pairs of a sub-round on four waves, one per
+// SIMD), so the scalar rotation arithmetic of four pairs shares each
+// instruction, and in the cross sub-rounds a row keeps its block-bp column
+// in registers while the block-bq columns pass through LDS.  Blocks stay in
+// place in global memory, so
 // the kernel boundary between rounds is the only synchronization.  A sweep
 // is nblk-1 rounds; the SVDs of all randUTV steps advance together (grid.y
 // = matrix), and a matrix stops as soon as a whole sweep rotated nothing:
@@ -24,6 +29,7 @@
 // e_1, e_2, ...  Matrices wider than kMaxLdsN use a single-workgroup
 // global-memory kernel.
 #include <algorithm>
+#include <utility>
 
 #include "common.h"
 
@@ -32,8 +38,12 @@ namespace {
 
 constexpr int MAXN = 1024;
 constexpr int kBW = 16;          // Jacobi block width
-constexpr int kRoundThreads = 64 * kBW;  // one wave per column pair of a sub-round
+constexpr int kRoundThreads = 16 * kBW;  // a 16-lane row for each of the kBW pairs of a sub-round
 constexpr int kMaxLdsN = 256;    // largest order handled by the LDS block kernel
+// Sweeps run as block rounds (a launch per round); the rest of the budget,
+// needed only by matrices not converged by then, runs in one launch.  The
+// factorization's b x b blocks take about 11 sweeps.
+constexpr int kBlockSweeps = 14;
 
 // DPP move of a double (two 32-bit halves) with control CTRL.
 template <int CTRL>
@@ -61,7 +71,58 @@ __device__ inline double wave_sum(double v) {
   return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
+// The largest value over the wave and its index, the smallest index among
+// equal values (a total order, so the reduction tree does not matter), in
+// every lane.  Same butterflies as wave_sum; called with all lanes active.
+template <int CTRL>
+__device__ inline void argmax_step(double& best, int& bi) {
+  const double ob = dpp_d<CTRL>(best);
+  const int oi = __builtin_amdgcn_update_dpp(0, bi, CTRL, 0xF, 0xF, false);
+  if (ob > best || (ob == best && oi < bi)) best = ob, bi = oi;
+}
+__device__ inline void wave_argmax(double& best, int& bi) {
+  argmax_step<0xB1>(best, bi);
+  argmax_step<0x4E>(best, bi);
+  argmax_step<0x141>(best, bi);
+  argmax_step<0x140>(best, bi);
+  double b = lane_d(best, 0);
+  int i = __builtin_amdgcn_readlane(bi, 0);
+#pragma unroll
+  for (int r = 16; r < 64; r += 16) {
+    const double ob = lane_d(best, r);
+    const int oi = __builtin_amdgcn_readlane(bi, r);
+    if (ob > b || (ob == b && oi < i)) b = ob, i = oi;
+  }
+  best = b, bi = i;
+}
+
+// Sum over the 16 lanes of a DPP row (the first four steps of wave_sum), in
+// every lane of the row.  Called with all lanes active.
+__device__ inline double row_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+
 __device__ inline double jacobi_tol(int nb) { return 4.0 * 2.220446049250313e-16 * sqrt((double)nb); }
+
+// The rotation (c, s) of the one-sided Jacobi method for two columns with
+// squared norms al, be and inner product ga: [x, y] <- [c x - s y, s x + c y]
+// makes them orthogonal.  False if they already are, to tolerance.
+__device__ inline bool jacobi_cs(double al, double be, double ga, double tol, double* c,
+                                 double* s) {
+  if (ga == 0.0 || al == 0.0 || be == 0.0) return false;
+  if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  double t;
+  if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+  else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  *c = 1.0 / sqrt(1.0 + t * t);
+  *s = *c * t;
+  return true;
+}
 
 // Rotate columns (wp, wq) of W and (vp, vq) of V so that wp^T wq = 0, if
 // they are not already orthogonal to tolerance.  One wave; returns true if
@@ -78,13 +139,8 @@ __device__ inline bool rotate_pair(double* wp, double* wq, double* vp, double* v
   al = wave_sum(al);
   be = wave_sum(be);
   ga = wave_sum(ga);
-  if (ga == 0.0 || al == 0.0 || be == 0.0) return false;
-  if (fabs(ga) <= tol * sqrt(al) * sqrt(be)) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  double t;
-  if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-  else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+  double c, s;
+  if (!jacobi_cs(al, be, ga, tol, &c, &s)) return false;
   for (int i = lane; i < n; i += 64) {
     const double x = wp[i], y = wq[i];
     wp[i] = c * x - s * y;
@@ -110,19 +166,39 @@ __device__ inline void rr_pair(int n2, int r, int k, int* p, int* q) {
 }
 
 // From the orthogonalized W (= U Sigma) and V in global memory: sort by
-// ||w_j||, normalize, complete zero columns, fix signs.  Whole workgroup.
-__device__ void finish_svd(int nb, int ld, const double* W, const double* V, double* Uo,
-                           double* Vo, double* Do, double* sig, int* rank) {
+// ||w_j||, normalize, complete zero columns, fix signs.  Whole workgroup;
+// sig, ssig, sgn (doubles) and rank (ints) are LDS arrays of nb entries.
+__device__ void finish_svd(int nb, int ld, const double* __restrict__ W,
+                           const double* __restrict__ V, double* __restrict__ Uo,
+                           double* __restrict__ Vo, double* __restrict__ Do, double* sig,
+                           double* ssig, double* sgn, int* rank) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = blockDim.x >> 6;
-  for (int j = wave; j < nb; j += nw) {
-    double s = 0.0;
+  // Per column j (unsorted): sigma_j = ||w_j|| and the sign that makes the
+  // largest-magnitude entry of v_j positive (first index on ties).
+  // Four columns per wave at a time, so that their loads are in flight together.
+  for (int j0 = 4 * wave; j0 < nb; j0 += 4 * nw) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0}, best[4] = {-1.0, -1.0, -1.0, -1.0};
+    int bi[4] = {0, 0, 0, 0};
     for (int i = lane; i < nb; i += 64) {
-      const double x = W[i + (int64_t)j * ld];
-      s += x * x;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int j = j0 + k < nb ? j0 + k : j0;
+        const double x = W[i + (int64_t)j * ld];
+        const double a = fabs(V[i + (int64_t)j * ld]);
+        s[k] += x * x;
+        if (a > best[k]) best[k] = a, bi[k] = i;
+      }
     }
-    s = wave_sum(s);
-    if (lane == 0) sig[j] = sqrt(s);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double sk = wave_sum(s[k]);
+      wave_argmax(best[k], bi[k]);
+      if (lane == 0 && j0 + k < nb) {
+        sig[j0 + k] = sqrt(sk);
+        sgn[j0 + k] = V[bi[k] + (int64_t)(j0 + k) * ld] < 0.0 ? -1.0 : 1.0;
+      }
+    }
   }
   __syncthreads();
   for (int j = tid; j < nb; j += blockDim.x) {
@@ -132,18 +208,40 @@ __device__ void finish_svd(int nb, int ld, const double* W, const double* V, dou
     rank[j] = rk;
   }
   __syncthreads();
-  for (int idx = tid; idx < nb * nb; idx += blockDim.x) {
-    const int i = idx % nb, j = idx / nb;
-    const int o = rank[j];
-    const double sj = sig[j];
-    Vo[i + (int64_t)o * ld] = V[i + (int64_t)j * ld];
-    Uo[i + (int64_t)o * ld] = sj > 0.0 ? W[i + (int64_t)j * ld] / sj : 0.0;
-    if (i == 0) Do[o] = sj;
+  for (int j = tid; j < nb; j += blockDim.x) ssig[rank[j]] = sig[j];
+  // Eight entries per thread at a time, their loads issued together.
+  const int nbt = blockDim.x;
+  for (int base = 0; base < nb * nb; base += 8 * nbt) {
+    double wv[8], vv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int idx = base + k * nbt + tid;
+      const int i = idx % nb, j = idx / nb;
+      const bool in = idx < nb * nb;
+      wv[k] = in ? W[i + (int64_t)j * ld] : 0.0;
+      vv[k] = in ? V[i + (int64_t)j * ld] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int idx = base + k * nbt + tid;
+      if (idx >= nb * nb) break;
+      const int i = idx % nb, j = idx / nb;
+      const int o = rank[j];
+      const double sj = sig[j], g = sgn[j];
+      Vo[i + (int64_t)o * ld] = g * vv[k];
+      Uo[i + (int64_t)o * ld] = sj > 0.0 ? g * (wv[k] / sj) : 0.0;
+      if (i == 0) Do[o] = sj;
+    }
   }
   __syncthreads();
-  if (wave == 0) {
+  // Columns with sigma = 0 (the last ones): Gram-Schmidt on e_1, e_2, ...
+  // against the columns before them, then the sign of that column's pair.
+  if (wave == 0 && !(ssig[nb - 1] > 0.0)) {
     for (int j = 0; j < nb; ++j) {
-      if (Do[j] > 0.0) continue;
+      if (ssig[j] > 0.0) continue;  // (a NaN is completed too)
+      double g = 1.0;
+      for (int k = 0; k < nb; ++k)
+        if (rank[k] == j) g = sgn[k];
       for (int e = 0; e < nb; ++e) {
         for (int i = lane; i < nb; i += 64) Uo[i + (int64_t)j * ld] = i == e ? 1.0 : 0.0;
         for (int pass = 0; pass < 2; ++pass) {
@@ -161,36 +259,9 @@ __device__ void finish_svd(int nb, int ld, const double* W, const double* V, dou
         }
         nr = sqrt(wave_sum(nr));
         if (nr > 0.5 / sqrt((double)nb)) {
-          for (int i = lane; i < nb; i += 64) Uo[i + (int64_t)j * ld] /= nr;
+          for (int i = lane; i < nb; i += 64) Uo[i + (int64_t)j * ld] = g * (Uo[i + (int64_t)j * ld] / nr);
           break;
         }
-      }
-    }
-  }
-  __syncthreads();
-  for (int j = wave; j < nb; j += nw) {
-    double best = -1.0;
-    int bi = 0;
-    for (int i = lane; i < nb; i += 64) {
-      const double x = fabs(Vo[i + (int64_t)j * ld]);
-      if (x > best) {
-        best = x;
-        bi = i;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (Vo[bi + (int64_t)j * ld] < 0.0) {
-      for (int i = lane; i < nb; i += 64) {
-        Vo[i + (int64_t)j * ld] = -Vo[i + (int64_t)j * ld];
-        Uo[i + (int64_t)j * ld] = -Uo[i + (int64_t)j * ld];
       }
     }
   }
@@ -215,12 +286,61 @@ __global__ void k_bj_init(const int* __restrict__ nbs, int ld, const double* __r
     for (int s = threadIdx.x; s < max_sweeps; s += blockDim.x) rotcount[mi * max_sweeps + s] = 0;
 }
 
+// Rows i = l16 + 16 t (t < NT) of two columns x, y held in registers,
+// rotated by the Jacobi rotation of the pair when `ok` and they are not
+// orthogonal to tolerance; otherwise (c, s) = (1, 0) leaves them exactly as
+// they are, so the code has no branch.  One 16-lane row per pair; every
+// lane of the wave calls it (the row sums use DPP).
+template <int NT>
+__device__ inline bool rotate_regs(double (&xw)[NT], double (&xv)[NT], double (&yw)[NT],
+                                   double (&yv)[NT], double tol, bool ok) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    al += xw[t] * xw[t];
+    be += yw[t] * yw[t];
+    ga += xw[t] * yw[t];
+  }
+  al = row_sum(al);
+  be = row_sum(be);
+  ga = row_sum(ga);
+  double c = 1.0, s = 0.0;
+  const bool rot = ok && jacobi_cs(al, be, ga, tol, &c, &s);
+  if (!rot) c = 1.0, s = 0.0;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double x = xw[t], y = yw[t];
+    xw[t] = c * x - s * y;
+    yw[t] = s * x + c * y;
+    const double u = xv[t], v = yv[t];
+    xv[t] = c * u - s * v;
+    yv[t] = s * u + c * v;
+  }
+  return rot;
+}
+
+// A column of the LDS block: rows l16 + 16 t; the rows from nb to 16 NT
+// hold zeros, which rotations keep.
+template <int NT>
+__device__ inline void lds_col_load(double (&r)[NT], const double* col, int l16) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) r[t] = col[l16 + 16 * t];
+}
+template <int NT>
+__device__ inline void lds_col_store(const double (&r)[NT], double* col, int l16) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) col[l16 + 16 * t] = r[t];
+}
+
+// One round of the block tournament: every column pair across blocks bp and
+// bq (and in round 0 the pairs inside each of them).  NT = ceil(ld / 16)
+// rows per lane.
+template <int NT>
 __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restrict__ nbs, int ld,
                                                   double* __restrict__ Wk, double* __restrict__ Vk,
                                                   int64_t strideUV, int* __restrict__ rotcount,
                                                   int max_sweeps, int sweep, int round) {
   extern __shared__ double sm[];
-  __shared__ int srot;
   const int mi = blockIdx.y, pi = blockIdx.x;
   const int nb = nbs[mi];
   const int nblk = (nb + kBW - 1) / kBW;
@@ -229,10 +349,11 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
   if (sweep > 0 && rotcount[mi * max_sweeps + sweep - 1] == 0) return;  // converged
   int bp, bq;
   rr_pair(nblk2, round, pi, &bp, &bq);
-  const int ldl = nb | 1;
+  constexpr int ldl = 16 * NT + 1;  // LDS column stride: 16 NT rows, odd
   double* sW = sm;
   double* sV = sm + 2 * kBW * ldl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int slot = wave * 4 + (lane >> 4), l16 = lane & 15;  // pair index, lane in the row
   double* W = Wk + mi * strideUV;
   double* V = Vk + mi * strideUV;
   auto gcol = [&](int c) -> int {  // global column of local column c, or -1
@@ -240,50 +361,92 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
     const int g = blk * kBW + (c % kBW);
     return (blk < nblk && g < nb) ? g : -1;
   };
-  // Column c of the pair per wave, rows lane-strided (no index division).
-  for (int c = wave; c < 2 * kBW; c += kRoundThreads / 64) {
-    const int g = gcol(c);
-    for (int i = lane; i < nb; i += 64) {
-      sW[c * ldl + i] = g >= 0 ? W[i + (int64_t)g * ld] : 0.0;
-      sV[c * ldl + i] = g >= 0 ? V[i + (int64_t)g * ld] : 0.0;
+  // Wave w loads columns w, w + 4, ... of the pair, rows lane + 64 u, and
+  // issues every load before its first LDS store: with one workgroup per CU
+  // the round is otherwise bound by the latency of these loads.
+  constexpr int NU = (NT + 3) / 4;  // 64-row chunks per column
+  constexpr int kCols = 2 * kBW / (kRoundThreads / 64);
+  {
+    double lw[kCols][NU], lv[kCols][NU];
+#pragma unroll
+    for (int v = 0; v < kCols; ++v) {
+      const int g = gcol(wave + 4 * v);
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int i = lane + 64 * u;
+        const bool in = g >= 0 && i < nb;
+        lw[v][u] = in ? W[i + (int64_t)g * ld] : 0.0;
+        lv[v][u] = in ? V[i + (int64_t)g * ld] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < kCols; ++v) {
+      const int c = wave + 4 * v;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int i = lane + 64 * u;
+        if (i < 16 * NT) {  // zeros from row nb on
+          sW[c * ldl + i] = lw[v][u];
+          sV[c * ldl + i] = lv[v][u];
+        }
+      }
     }
   }
   const double tol = jacobi_tol(nb);
-  if (tid == 0) srot = 0;
+  bool rot = false;
+  double xw[NT], xv[NT], yw[NT], yv[NT];
   __syncthreads();
   // Round 0 of a sweep also visits the pairs inside each block (every block
   // is in exactly one pair per round): round-robin over the kBW columns of
-  // each of the two blocks.
+  // each of the two blocks, kBW / 2 pairs per block and sub-round.
   if (round == 0) {
     for (int r = 0; r < kBW - 1; ++r) {
-      for (int k = wave; k < kBW; k += kRoundThreads / 64) {
-        const int half = k / (kBW / 2), kk = k % (kBW / 2);
-        int p, q;
-        rr_pair(kBW, r, kk, &p, &q);
-        p += half * kBW;
-        q += half * kBW;
-        if (gcol(p) < 0 || gcol(q) < 0) continue;
-        if (rotate_pair(sW + p * ldl, sW + q * ldl, sV + p * ldl, sV + q * ldl, nb, lane, tol) &&
-            lane == 0)
-          srot = 1;
-      }
+      const int half = slot / (kBW / 2), kk = slot % (kBW / 2);
+      int p, q;
+      rr_pair(kBW, r, kk, &p, &q);
+      p += half * kBW;
+      q += half * kBW;
+      lds_col_load(xw, sW + p * ldl, l16);
+      lds_col_load(xv, sV + p * ldl, l16);
+      lds_col_load(yw, sW + q * ldl, l16);
+      lds_col_load(yv, sV + q * ldl, l16);
+      rot |= rotate_regs(xw, xv, yw, yv, tol, gcol(p) >= 0 && gcol(q) >= 0);
+      lds_col_store(xw, sW + p * ldl, l16);
+      lds_col_store(xv, sV + p * ldl, l16);
+      lds_col_store(yw, sW + q * ldl, l16);
+      lds_col_store(yv, sV + q * ldl, l16);
       __syncthreads();
     }
   }
   // Cross pairs (p in block bp, q in block bq): kBW sub-rounds of kBW
-  // disjoint pairs (k, kBW + (k + r) mod kBW).
+  // disjoint pairs (k, kBW + (k + r) mod kBW).  Row k keeps column k in
+  // registers throughout; the columns of block bq move through LDS.
+  const int p = slot;
+  const bool okp = gcol(p) >= 0;
+  lds_col_load(xw, sW + p * ldl, l16);
+  lds_col_load(xv, sV + p * ldl, l16);
   for (int r = 0; r < kBW; ++r) {
-    for (int k = wave; k < kBW; k += kRoundThreads / 64) {
-      const int p = k, q = kBW + (k + r) % kBW;
-      if (gcol(p) < 0 || gcol(q) < 0) continue;
-      if (rotate_pair(sW + p * ldl, sW + q * ldl, sV + p * ldl, sV + q * ldl, nb, lane, tol) &&
-          lane == 0)
-        srot = 1;
-    }
+    const int q = kBW + (slot + r) % kBW;
+    lds_col_load(yw, sW + q * ldl, l16);
+    lds_col_load(yv, sV + q * ldl, l16);
+    rot |= rotate_regs(xw, xv, yw, yv, tol, okp && gcol(q) >= 0);
+    lds_col_store(yw, sW + q * ldl, l16);
+    lds_col_store(yv, sV + q * ldl, l16);
     __syncthreads();
   }
-  const bool any = srot != 0;
-  for (int c = wave; c < 2 * kBW; c += kRoundThreads / 64) {
+  // Block bp's columns from registers, block bq's from LDS.
+  if (okp) {
+    const int g = gcol(p);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int i = l16 + 16 * t;
+      if (i < nb) {
+        W[i + (int64_t)g * ld] = xw[t];
+        V[i + (int64_t)g * ld] = xv[t];
+      }
+    }
+  }
+  for (int c = kBW + wave; c < 2 * kBW; c += kRoundThreads / 64) {
     const int g = gcol(c);
     if (g < 0) continue;
     for (int i = lane; i < nb; i += 64) {
@@ -291,10 +454,17 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
       V[i + (int64_t)g * ld] = sV[c * ldl + i];
     }
   }
-  if (any && tid == 0) atomicAdd(&rotcount[mi * max_sweeps + sweep], 1);
+  if (__syncthreads_or(rot) && tid == 0) atomicAdd(&rotcount[mi * max_sweeps + sweep], 1);
 }
 
-__global__ __launch_bounds__(256) void k_bj_finish(const int* __restrict__ nbs, int ld,
+using RoundFn = void (*)(const int*, int, double*, double*, int64_t, int*, int, int, int);
+template <int... NTs>
+RoundFn round_fn(int nt, std::integer_sequence<int, NTs...>) {
+  RoundFn fns[] = {k_bj_round<NTs + 1>...};
+  return fns[nt - 1];
+}
+
+__global__ __launch_bounds__(1024) void k_bj_finish(const int* __restrict__ nbs, int ld,
                                                    const double* __restrict__ Wk,
                                                    const double* __restrict__ Vk,
                                                    int64_t strideUV, double* __restrict__ Us,
@@ -303,13 +473,13 @@ __global__ __launch_bounds__(256) void k_bj_finish(const int* __restrict__ nbs, 
                                                    const int* __restrict__ rotcount,
                                                    int max_sweeps, int* __restrict__ status,
                                                    int* __restrict__ fail) {
-  __shared__ double sig[kMaxLdsN];
+  __shared__ double sig[kMaxLdsN], ssig[kMaxLdsN], sgn[kMaxLdsN];
   __shared__ int rank[kMaxLdsN];
   const int mi = blockIdx.x;
   const int nb = nbs[mi];
   if (nb > 0)
     finish_svd(nb, ld, Wk + mi * strideUV, Vk + mi * strideUV, Us + mi * strideUV,
-               Vs + mi * strideUV, D + mi * strideD, sig, rank);
+               Vs + mi * strideUV, D + mi * strideD, sig, ssig, sgn, rank);
   if (threadIdx.x == 0) {
     int st = -1;
     for (int s = 0; s < max_sweeps; ++s)
@@ -323,6 +493,57 @@ __global__ __launch_bounds__(256) void k_bj_finish(const int* __restrict__ nbs, 
   }
 }
 
+// Cyclic one-sided Jacobi sweeps first .. max_sweeps - 1 over W and V in
+// global memory, one workgroup (a wave per pair of a round-robin round),
+// until a sweep rotates nothing.  Returns the number of sweeps counted from
+// 0 (the converged sweep included), or -1 if the budget ran out.  With
+// `swept` set, sweep s records whether it rotated in swept[s].  `rotated`
+// is an LDS int.
+__device__ int cyclic_sweeps(int nb, int ld, double* W, double* V, int first, int max_sweeps,
+                             int* swept, int* rotated) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  const int n2 = nb + (nb & 1);
+  const double tol = jacobi_tol(nb);
+  if (nb <= 1) return first;
+  for (int sw = first; sw < max_sweeps; ++sw) {
+    if (tid == 0) *rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < n2 - 1; ++r) {
+      for (int k = wave; k < n2 / 2; k += nw) {
+        int p, q;
+        rr_pair(n2, r, k, &p, &q);
+        if (p >= nb || q >= nb) continue;
+        if (rotate_pair(W + (int64_t)p * ld, W + (int64_t)q * ld, V + (int64_t)p * ld,
+                        V + (int64_t)q * ld, nb, lane, tol) &&
+            lane == 0)
+          *rotated = 1;
+      }
+      __syncthreads();
+    }
+    const bool conv = *rotated == 0;
+    if (swept && tid == 0) swept[sw] = conv ? 0 : 1;
+    __syncthreads();
+    if (conv) return sw + 1;
+  }
+  return -1;
+}
+
+// The sweeps of the budget after the first kBlockSweeps, for the matrices
+// that the block rounds have not brought to convergence by then (rare):
+// one workgroup per matrix, so that this part costs one launch instead of
+// a launch per round when, as usual, every matrix has converged.
+__global__ __launch_bounds__(1024) void k_bj_tail(const int* __restrict__ nbs, int ld,
+                                                  double* __restrict__ Wk, double* __restrict__ Vk,
+                                                  int64_t strideUV, int* __restrict__ rotcount,
+                                                  int max_sweeps, int first) {
+  __shared__ int rotated;
+  const int mi = blockIdx.x;
+  const int nb = nbs[mi];
+  if (nb <= 1 || rotcount[mi * max_sweeps + first - 1] == 0) return;
+  (void)cyclic_sweeps(nb, ld, Wk + mi * strideUV, Vk + mi * strideUV, first, max_sweeps,
+                      rotcount + mi * max_sweeps, &rotated);
+}
+
 // ------------------------------------------------ single-workgroup fallback
 __global__ __launch_bounds__(256) void k_jacobi(const int* __restrict__ nbs, int ld,
                                                 const double* __restrict__ R, int64_t strideR,
@@ -332,7 +553,7 @@ __global__ __launch_bounds__(256) void k_jacobi(const int* __restrict__ nbs, int
                                                 double* __restrict__ Wk, double* __restrict__ Vk,
                                                 int* __restrict__ status, int max_sweeps,
                                                 int* __restrict__ fail) {
-  __shared__ double sig[MAXN];
+  __shared__ double sig[MAXN], ssig[MAXN], sgn[MAXN];
   __shared__ int rank[MAXN];
   __shared__ int rotated;
   const int mi = blockIdx.x;
@@ -351,32 +572,12 @@ __global__ __launch_bounds__(256) void k_jacobi(const int* __restrict__ nbs, int
     V[i + (int64_t)j * ld] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int n2 = nb + (nb & 1);
-  const double tol = jacobi_tol(nb);
-  int sweeps = 0;
-  bool conv = nb == 1;
-  for (int sw = 0; sw < max_sweeps && !conv; ++sw) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int r = 0; r < n2 - 1; ++r) {
-      for (int k = wave; k < n2 / 2; k += 4) {
-        int p, q;
-        rr_pair(n2, r, k, &p, &q);
-        if (p >= nb || q >= nb) continue;
-        if (rotate_pair(W + (int64_t)p * ld, W + (int64_t)q * ld, V + (int64_t)p * ld,
-                        V + (int64_t)q * ld, nb, lane, tol) &&
-            lane == 0)
-          rotated = 1;
-      }
-      __syncthreads();
-    }
-    ++sweeps;
-    conv = rotated == 0;
-    __syncthreads();
-  }
-  finish_svd(nb, ld, W, V, Us + mi * strideUV, Vs + mi * strideUV, D + mi * strideD, sig, rank);
+  const int sweeps = cyclic_sweeps(nb, ld, W, V, 0, max_sweeps, nullptr, &rotated);
+  const bool conv = sweeps >= 0;
+  finish_svd(nb, ld, W, V, Us + mi * strideUV, Vs + mi * strideUV, D + mi * strideD, sig, ssig,
+             sgn, rank);
   if (tid == 0) {
-    status[mi] = conv ? sweeps : -1;
+    status[mi] = sweeps;
     if (!conv && fail) atomicOr(fail, 1);
   }
 }
@@ -397,13 +598,19 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
     return hipGetLastError();
   }
   static bool attr_set = false;
-  const size_t shmem = (size_t)4 * kBW * (ld | 1) * sizeof(double);
+  constexpr int kMaxNT = kMaxLdsN / 16;
+  // LDS of a round: W and V columns of two blocks, 16 NT + 1 rows each.
+  const size_t shmem = (size_t)4 * kBW * (16 * ((ld + 15) / 16) + 1) * sizeof(double);
+  const auto nts = std::make_integer_sequence<int, kMaxNT>();
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_bj_round, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)((size_t)4 * kBW * (kMaxLdsN | 1) * sizeof(double)));
+    for (int nt = 1; nt <= kMaxNT; ++nt)
+      (void)hipFuncSetAttribute((const void*)round_fn(nt, nts),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)((size_t)4 * kBW * (kMaxLdsN | 1) * sizeof(double)));
     (void)hipGetLastError();
     attr_set = true;
   }
+  const RoundFn round = round_fn((ld + 15) / 16, nts);
   // Per-matrix sweep counters follow the status words: count * max_sweeps ints.
   int* rotcount = status + count;
   hipLaunchKernelGGL(k_bj_init, dim3(16, count), dim3(256), 0, st, nb_dev, ld, R, strideR, Wk, Vk,
@@ -415,11 +622,15 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
   // later round (its workgroups return at once), and k_bj_finish reports a
   // matrix that still rotated in the last sweep of the budget.  The host
   // never waits for the device here.
-  for (int sw = 0; sw < max_sweeps; ++sw)
+  const int block_sweeps = std::min(max_sweeps, kBlockSweeps);
+  for (int sw = 0; sw < block_sweeps; ++sw)
     for (int r = 0; r < nblk2 - 1; ++r)
-      hipLaunchKernelGGL(k_bj_round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st,
-                         nb_dev, ld, Wk, Vk, strideUV, rotcount, max_sweeps, sw, r);
-  hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(256), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
+      hipLaunchKernelGGL(round, dim3(nblk2 / 2, count), dim3(kRoundThreads), shmem, st, nb_dev,
+                         ld, Wk, Vk, strideUV, rotcount, max_sweeps, sw, r);
+  if (max_sweeps > block_sweeps)
+    hipLaunchKernelGGL(k_bj_tail, dim3(count), dim3(1024), 0, st, nb_dev, ld, Wk, Vk, strideUV,
+                       rotcount, max_sweeps, block_sweeps);
+  hipLaunchKernelGGL(k_bj_finish, dim3(count), dim3(1024), 0, st, nb_dev, ld, Wk, Vk, strideUV, Us,
                      Vs, D, strideD, rotcount, max_sweeps, status, fail);
   prof_done(st, slot, PC_SVD, 0.0, 0.0);
   return hipGetLastError();
