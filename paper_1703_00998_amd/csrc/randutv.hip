@@ -734,9 +734,9 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   }
   // Batched SVDs of the stashed R blocks, then fold the rotations back:
   // T(I2,J2) = Ds, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) = T(I1,J2) Vs,
-  // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.  The SVDs and T's part run
-  // while the U / V stream finishes its last products; U and V's part
-  // waits for it.
+  // U(:,I2) = U(:,I2) Us, V(:,J2) = V(:,J2) Vs.  The SVDs run while the
+  // U / V stream finishes its last products; then T's part runs on the main
+  // stream and U and V's part on the U / V stream.
   auto width = [&](int i) { return i == nsvd - 1 ? last_w : B; };
   // Economy U by backward accumulation: for block i (last first), the
   // columns right of it (already formed) times H_i = I - Uh_i Tw_i Uh_i^T,
@@ -759,6 +759,24 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   hipLaunchKernelGGL(k_set_ints, dim3(1), dim3(256), 0, st, nbs, nsvd, B, last_w);
   HIPCHK(batched_svd(st, nsvd, nbs, B, Rst, (int64_t)B * B, Ust, Vst, (int64_t)B * B, Dd, B, Jw, Jv,
                      jstatus, kJacobiSweeps, &blk->svd_fail));
+  // U and V's part of the fold-back on the U / V stream (once it has formed
+  // them), beside T's part on the main stream; its products go through Ws.
+  HIPCHK(to_side(kVR));
+  for (int i = 0; i < nsvd && (formU || formV); ++i) {
+    const int r0 = i * B, w = width(i);
+    const double* Us = Ust + (size_t)i * B * B;
+    const double* Vs = Vst + (size_t)i * B * B;
+    if (formU) {
+      double* blk = U + (int64_t)r0 * ldu;
+      HIPCHK(gemm(ss, PREC_FP64, false, false, M, w, w, 1.0, blk, ldu, Us, B, 0.0, Ws, MN, nullptr, 0));
+      HIPCHK(copy_matrix(ss, M, w, Ws, MN, blk, ldu));
+    }
+    if (formV) {
+      double* blk = V + (int64_t)r0 * ldv;
+      HIPCHK(gemm(ss, PREC_FP64, false, false, N, w, w, 1.0, blk, ldv, Vs, B, 0.0, Ws, MN, nullptr, 0));
+      HIPCHK(copy_matrix(ss, N, w, Ws, MN, blk, ldv));
+    }
+  }
   for (int i = 0; i < nsvd; ++i) {
     const int r0 = i * B, w = width(i);
     const double* Us = Ust + (size_t)i * B * B;
@@ -778,21 +796,6 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     }
   }
   HIPCHK(join_side());
-  for (int i = 0; i < nsvd && (formU || formV); ++i) {
-    const int r0 = i * B, w = width(i);
-    const double* Us = Ust + (size_t)i * B * B;
-    const double* Vs = Vst + (size_t)i * B * B;
-    if (formU) {
-      double* blk = U + (int64_t)r0 * ldu;
-      HIPCHK(gemm(st, PREC_FP64, false, false, M, w, w, 1.0, blk, ldu, Us, B, 0.0, Ftmp, M, nullptr, 0));
-      HIPCHK(copy_matrix(st, M, w, Ftmp, M, blk, ldu));
-    }
-    if (formV) {
-      double* blk = V + (int64_t)r0 * ldv;
-      HIPCHK(gemm(st, PREC_FP64, false, false, N, w, w, 1.0, blk, ldv, Vs, B, 0.0, Ftmp, N, nullptr, 0));
-      HIPCHK(copy_matrix(st, N, w, Ftmp, N, blk, ldv));
-    }
-  }
   HIPCHK(status_done(st, blk, k_done));
   if (k_out) {
     *k_out = k_done;
