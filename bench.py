@@ -119,12 +119,13 @@ def cpu_baseline(n_sample, b, q):
 
 def dominant_class(prof, arith=None):
     """The thin-GEMM kernel class (one k_gemm instantiation: transposes,
-    arithmetic, tile) with the most time, optionally among the classes of
-    one arithmetic (or of a tuple of them).  The panel factorizations' own products are timed inside the
+    arithmetic, tile, and _uv for the U / V stream's products) with the most
+    time, optionally among the classes of one arithmetic (or of a tuple of
+    them).  The panel factorizations' own products are timed inside the
     panel_qr class, so every launch of a GEMM class is a launch of the
     factorization's thin products (sampling, updates, U / V, fold-back)."""
     gem = {k: v for k, v in prof.items()
-           if k.startswith("gemm_") and len(k.split("_")) == 4 and v[3] > 0
+           if k.startswith("gemm_") and k.split("_")[4:] in ([], ["uv"]) and v[3] > 0
            and (arith is None or k.split("_")[2] in
                 ((arith,) if isinstance(arith, str) else tuple(arith)))}
     return max(gem, key=lambda k: gem[k][0]) if gem else None
@@ -134,10 +135,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 def kernel_symbol(cls):
-    """k_gemm instantiation of a class name gemm_<op(A)op(B)>_<arith>_t<tile>."""
-    _, op, arith, tile = cls.split("_")
+    """k_gemm instantiation of a class name gemm_<op(A)op(B)>_<arith>_t<tile>,
+    with a _uv suffix for the U / V stream's products (ROLE 2; else 0)."""
+    parts = cls.split("_")
+    _, op, arith, tile = parts[:4]
+    role = 2 if parts[4:] == ["uv"] else 0
     return (f"k_gemm<PREC_{arith.upper()}, {'true' if op[0] == 't' else 'false'}, "
-            f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, 2, 2>")
+            f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, 2, 2, {role}>")
 
 
 def roofline_of(dom, prof_dom, workload):

@@ -176,8 +176,8 @@ int randutv_status(const void* work, size_t work_bytes, int64_t* k_out, void* st
  * library, one per GPU, held until the process ends.  The call allocates
  * nothing (no hipMalloc, hipFree, stream or event creation); U and V are
  * updated on `stream` itself.  Sizes whose randutv_workspace_size exceeds
- * 128 MiB (for example 4000 x 4000 with b = 256; 4000 x 4000 with b = 128
- * fits) return RANDUTV_E_WORKSPACE before any work is enqueued.  All calls
+ * 128 MiB (for example 4000 x 4000 with b = 128 or 256; 3800 x 3800 with
+ * b = 128 fits) return RANDUTV_E_WORKSPACE before any work is enqueued.  All calls
  * on one GPU share its array: calls that overlap in time on one GPU (on
  * different streams or host threads) race; calls on one stream do not.
  * Status through k_out as for randutv_factor (12 k_out, 13 stream).

@@ -23,7 +23,10 @@ constexpr int kPanelMaxRows = 256;
 constexpr unsigned kSpinLimit = 1u << 20;
 // Largest split-K factor of the thin GEMMs.
 constexpr int kMaxSplitK = 8;
-constexpr int kMaxSplitKSmall = 64;  // for outputs of at most 32 tiles of 64 x 64
+#ifndef MAX_SPLITK_SMALL
+#define MAX_SPLITK_SMALL 64
+#endif
+constexpr int kMaxSplitKSmall = MAX_SPLITK_SMALL;  // for outputs of at most 32 tiles of 64 x 64
 
 // Arithmetic of the thin-matrix products.  FP64, FP32 and BF16X3 have the
 // randutv_prec values of the same names; BF16X6 (three bf16 pieces per
@@ -48,7 +51,9 @@ inline Prec update_prec(int prec) {
 // 16*shape + 4*prec + 2*tb + ta; one class is one kernel instantiation),
 // then the other kernels.
 enum ProfClass { PC_GEMM_NN = 0, PC_GEMM_TN = 1, PC_GEMM_NT = 2, PC_GEMM_TT = 3,
-                 PC_SPLITK = 32, PC_PANEL, PC_SVD, PC_GEMM_SMALL, PC_COUNT };
+                 PC_SPLITK = 32, PC_PANEL, PC_SVD, PC_GEMM_SMALL,
+                 PC_UV,  // + op: the U / V stream's FP64 64 x 64 products
+                 PC_COUNT = PC_UV + 4 };
 bool prof_on();
 // Start event of a launch of class `cls`; returns a slot, or -1 when off or
 // when timing is restricted to another class.
@@ -62,7 +67,8 @@ void prof_done(hipStream_t st, int slot, int cls, double flops, double bytes);
 // if ta/tb.  `splitws` (>= kMaxSplitK * M * N doubles, or NULL) enables
 // split-K for long reductions.  The arithmetic of the inner products is set
 // by `prec`; operands and C are FP64 in memory.
-// small_tiles forces 64 x 64 tiles (shorter workgroups, for the second stream).
+// small_tiles marks the U / V stream's products: 64 x 64 tiles (shorter
+// workgroups), ROLE 2 of k_gemm in FP64.
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc,

@@ -56,31 +56,33 @@ constexpr int slab_k() {
 // (the bf16 MFMA operand) as one 16-byte load.  NB buffers: two (the next
 // slab is stored while the current one is multiplied) except for the
 // three-piece BF16x6 slabs of 128 x 128 tiles, whose single buffer (48 KB)
-// keeps two workgroups per CU.
-template <int P, int BM, int BN>
+// keeps two workgroups per CU.  (A single buffer for the U / V stream's FP64
+// products, 17 KB, so that a panel kernel's 142 KB fit on a CU beside one of
+// them, made the panels' Cholesky kernels 2 ms faster per factorization but
+// the whole 3 ms slower.)
+template <int P, int BM, int BN, int NB>
 struct Slabs;
-template <int BM, int BN>
-struct Slabs<PREC_FP64, BM, BN> {
-  double A[2][slab_k<PREC_FP64, BM>()][BM + PAD];
-  double B[2][slab_k<PREC_FP64, BM>()][BN + PAD];
+template <int BM, int BN, int NB>
+struct Slabs<PREC_FP64, BM, BN, NB> {
+  double A[NB][slab_k<PREC_FP64, BM>()][BM + PAD];
+  double B[NB][slab_k<PREC_FP64, BM>()][BN + PAD];
 };
-template <int BM, int BN>
-struct Slabs<PREC_FP32, BM, BN> {
-  float A[2][slab_k<PREC_FP32, BM>()][BM + PAD];
-  float B[2][slab_k<PREC_FP32, BM>()][BN + PAD];
+template <int BM, int BN, int NB>
+struct Slabs<PREC_FP32, BM, BN, NB> {
+  float A[NB][slab_k<PREC_FP32, BM>()][BM + PAD];
+  float B[NB][slab_k<PREC_FP32, BM>()][BN + PAD];
 };
-template <int BM, int BN>
-struct Slabs<PREC_BF16X3, BM, BN> {
-  alignas(16) __bf16 Ah[2][4][BM][8];
-  alignas(16) __bf16 Al[2][4][BM][8];
-  alignas(16) __bf16 Bh[2][4][BN][8];
-  alignas(16) __bf16 Bl[2][4][BN][8];
+template <int BM, int BN, int NB>
+struct Slabs<PREC_BF16X3, BM, BN, NB> {
+  alignas(16) __bf16 Ah[NB][4][BM][8];
+  alignas(16) __bf16 Al[NB][4][BM][8];
+  alignas(16) __bf16 Bh[NB][4][BN][8];
+  alignas(16) __bf16 Bl[NB][4][BN][8];
 };
 template <int BM>
 constexpr int bf6_bufs() { return BM >= 128 ? 1 : 2; }
-template <int BM, int BN>
-struct Slabs<PREC_BF16X6, BM, BN> {
-  static constexpr int NB = bf6_bufs<BM>();
+template <int BM, int BN, int NB>
+struct Slabs<PREC_BF16X6, BM, BN, NB> {
   alignas(16) __bf16 Ah[NB][4][BM][8];
   alignas(16) __bf16 Am[NB][4][BM][8];
   alignas(16) __bf16 Al[NB][4][BM][8];
@@ -110,10 +112,11 @@ __device__ inline Bf3 split3(float x32) {
 // 128 x 128 tiles at 51-55 TFLOP/s on the n = 8000 shapes vs 20-26 without
 // it).  Operands are FP64 in memory for every arithmetic; the loader
 // converts.
-// ROLE tells apart two instantiations of the same code: 0 for the method's
-// thin products (sampling, trailing updates, U and V, fold-back), 1 for the
-// products inside the Householder panel factorizations, so that kernel
-// traces and counters attribute them separately.
+// ROLE tells apart instantiations of the same code, so that kernel traces
+// and counters attribute them separately: 0 for the method's thin products
+// on the main stream (sampling, trailing updates, fold-back of T), 1 for the
+// products inside the Householder panel factorizations, 2 for the U / V
+// stream's products.
 template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN, int ROLE>
 __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
     int M, int N, int K, int kper, const double* __restrict__ A, int64_t lda,
@@ -126,8 +129,8 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
   constexpr int LA = BM * BK / NT, LB = BN * BK / NT;  // elements per thread
   static_assert(LA * NT == BM * BK && LB * NT == BN * BK, "loader shape");
   static_assert(NT % BM == 0 && NT % BN == 0 && NT % BK == 0, "loader shape");
-  __shared__ Slabs<P, BM, BN> sl;
   constexpr int NBUF = P == PREC_BF16X6 ? bf6_bufs<BM>() : 2;
+  __shared__ Slabs<P, BM, BN, NBUF> sl;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
@@ -501,6 +504,13 @@ int g_panel_scope = 0;  // > 0 while a panel factorization enqueues its products
 
 void gemm_panel_scope(int delta) { g_panel_scope += delta; }
 
+#ifndef SMALL_SPLIT_MIN_K
+#define SMALL_SPLIT_MIN_K 64
+#endif
+// Least reduction depth per split of a small output (a Gram matrix of a tall
+// panel): its workgroups are latency-bound, so shorter splits finish sooner.
+constexpr int kSmallSplitMinK = SMALL_SPLIT_MIN_K;
+
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc, double* splitws,
@@ -546,7 +556,7 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
         shape == 1 && (prec == PREC_BF16X3 || prec == PREC_BF16X6 || prec == PREC_FP64);
     splits = small ? (1024 + tiles - 1) / tiles
                    : (two_per_cu ? std::max(1, 512 / tiles) : (512 + tiles - 1) / tiles);
-    splits = std::min(splits, K / (small ? 256 : 512));
+    splits = std::min(splits, K / (small ? kSmallSplitMinK : 512));
     splits = std::min(splits, small ? kMaxSplitKSmall : kMaxSplitK);
     while (splits > 1 && (size_t)splits * M * N > splitws_elems) --splits;
     if (splits < 1) splits = 1;
@@ -566,8 +576,9 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     al = 1.0;
     be = 0.0;
   }
-  const int cls = 16 * shape + 4 * (int)prec +
-                  (ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN));
+  const int op = ta ? (tb ? PC_GEMM_TT : PC_GEMM_TN) : (tb ? PC_GEMM_NT : PC_GEMM_NN);
+  const bool uv = small_tiles && prec == PREC_FP64;  // the U / V stream's products
+  const int cls = uv ? PC_UV + op : 16 * shape + 4 * (int)prec + op;
   const int slot = prof_mark(st, cls);
   if (prec == PREC_FP32)
     launch_p<PREC_FP32>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
@@ -575,6 +586,8 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
     launch_p<PREC_BF16X6>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else if (prec == PREC_BF16X3)
     launch_p<PREC_BF16X3>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else if (uv)
+    launch_p<PREC_FP64, 2>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else if (g_panel_scope > 0)
     launch_p<PREC_FP64, 1>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else

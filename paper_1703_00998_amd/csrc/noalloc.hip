@@ -10,8 +10,9 @@
 #include "../../include/randutv.h"
 #include "common.h"
 
-// 128 MiB: the workspace of a 4000 x 4000 factorization with b = 128 and U, V
-// formed (125 MiB) fits; larger ones are rejected.
+// 128 MiB: the workspace of a 3800 x 3800 factorization with b = 128 and U, V
+// formed (123 MiB) fits; larger ones (4000 x 4000 with b = 128 needs
+// 129 MiB) are rejected.
 constexpr size_t kScratchBytes = (size_t)128 << 20;
 static __device__ __align__(256) char scratch[kScratchBytes];
 

@@ -61,6 +61,7 @@ std::string class_name(int c) {
   if (c == PC_SVD) return "small_svd";
   if (c == PC_GEMM_SMALL) return "gemm_small_fp64";
   static const char* ops[4] = {"nn", "tn", "nt", "tt"};
+  if (c >= PC_UV) return std::string("gemm_") + ops[c - PC_UV] + "_fp64_t64_uv";
   static const char* precs[4] = {"fp64", "fp32", "bf16x3", "bf16x6"};
   static const char* tiles[2] = {"t64", "t128"};
   return std::string("gemm_") + ops[c % 4] + "_" + precs[(c / 4) % 4] + "_" + tiles[c / 16];

@@ -40,10 +40,16 @@ constexpr int kMaxPanelRows = kPanelMaxWGGlobal * kPanelMaxRows;
 // than 30 sweeps (their near-zero columns keep rotating at rounding level).
 constexpr int kJacobiSweeps = 40;
 
+// Reflector slots shared with the U / V stream (step i uses slot i % kSlots).
+#ifndef UV_SLOTS
+#define UV_SLOTS 3
+#endif
+constexpr int kSlots = UV_SLOTS;
+
 struct Layout {
-  size_t status, Y, Vh, Vh2, Vh3, Z, Uh, Uh2, Uh3, W, W2, Ws, W2s, C, C2, TwV, TwV2, TwV3, TwU, TwU2,
-      TwU3, tauV, tauU, Rst, TwUst,
-      Ust, Vst, D, Jw, Jv, Ftmp, split, nrm, ints, panel, hr, total;
+  size_t status, Y, Z, W, W2, Ws, W2s, C, C2, tauV, tauU, Rst, TwUst, Ust, Vst, D, Jw, Jv, Ftmp,
+      split, nrm, ints, panel, hr, total;
+  size_t Vh[kSlots], Uh[kSlots], TwV[kSlots], TwU[kSlots];  // reflector slots
   // Over-sampling (p > 0) only: QR and SVD of the extended sample.
   size_t VY, TwY, RY, UR, VR, JwR, JvR, tauY, DR, Cy, Cy2, intsY;
   size_t split_elems;
@@ -80,25 +86,17 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   };
   L.status = take(kStatusBytes);  // first: randutv_status reads it at offset 0
   L.Y = take((size_t)n * bp * d);
-  L.Vh = take(nb * d);
-  L.Vh2 = take(nb * d);
-  L.Vh3 = take(nb * d);
+  for (int k = 0; k < kSlots; ++k) L.Vh[k] = take(nb * d);
   L.Z = take((size_t)m * bp * d);
-  L.Uh = take(mb * d);
-  L.Uh2 = take(mb * d);
-  L.Uh3 = take(mb * d);
+  for (int k = 0; k < kSlots; ++k) L.Uh[k] = take(mb * d);
   L.W = take(mb * d);
   L.W2 = take(mb * d);
   L.Ws = take(std::max(mb, nb) * d);   // U / V stream products, leading dimension max(m, n)
   L.W2s = take(std::max(mb, nb) * d);
   L.C = take(nb * d);
   L.C2 = take(nb * d);
-  L.TwV = take(bb * d);
-  L.TwV2 = take(bb * d);
-  L.TwV3 = take(bb * d);
-  L.TwU = take(bb * d);
-  L.TwU2 = take(bb * d);
-  L.TwU3 = take(bb * d);
+  for (int k = 0; k < kSlots; ++k) L.TwV[k] = take(bb * d);
+  for (int k = 0; k < kSlots; ++k) L.TwU[k] = take(bb * d);
   L.tauV = take(b * d);
   L.tauU = take(b * d);
   L.Rst = take(s * bb * d);
@@ -134,8 +132,6 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   return L;
 }
 
-// Reflector slots shared with the U / V stream (step i uses slot i % kSlots).
-constexpr int kSlots = 3;
 
 // U and V accumulation runs on a second stream of the device (default
 // priority), ordered against the main stream by events: the panels and
@@ -206,9 +202,15 @@ SideCtx* side_ctx() {
 // n = 8000) bound that wait, at some cost in tail effects of the side
 // products (measured: 1024 columns, 129.4 ms per factorization against
 // 134.6 ms uncut; 512-1536 within 1 ms of that).
-constexpr int kSideChunk = 256;     // reduction chunk of the thin products W = X Vh
+#ifndef SIDE_CHUNK
+#define SIDE_CHUNK 256
+#endif
+#ifndef SIDE_COLS
+#define SIDE_COLS 1024
+#endif
+constexpr int kSideChunk = SIDE_CHUNK;  // reduction chunk of the thin products W = X Vh
 constexpr int kSideChunkUpd = 256;  // and of the rank-b updates X -= W2 Vh^T
-constexpr int kSideCols = 1024;     // output columns per launch
+constexpr int kSideCols = SIDE_COLS;  // output columns per launch
 hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha,
                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                      double* C, int64_t ldc, int chunk) {
@@ -527,10 +529,9 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   const int MN = std::max(M, N);  // leading dimension of the U / V stream products
   int* intsY = p > 0 ? (int*)(base + L.intsY) : nullptr;
 
-  double* const VhS[kSlots] = {dp(L.Vh), dp(L.Vh2), dp(L.Vh3)};
-  double* const UhS[kSlots] = {dp(L.Uh), dp(L.Uh2), dp(L.Uh3)};
-  double* const TwVS[kSlots] = {dp(L.TwV), dp(L.TwV2), dp(L.TwV3)};
-  double* const TwUS[kSlots] = {dp(L.TwU), dp(L.TwU2), dp(L.TwU3)};
+  double *VhS[kSlots], *UhS[kSlots], *TwVS[kSlots], *TwUS[kSlots];
+  for (int k = 0; k < kSlots; ++k)
+    VhS[k] = dp(L.Vh[k]), UhS[k] = dp(L.Uh[k]), TwVS[k] = dp(L.TwV[k]), TwUS[k] = dp(L.TwU[k]);
   constexpr int kVR = 0, kUR = kSlots, kVD = 2 * kSlots, kUD = 3 * kSlots, kJoin = 4 * kSlots;
 
   // Economy U (m x min(m, n)): each step's left reflectors are stored in U's

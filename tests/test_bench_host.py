@@ -28,13 +28,13 @@ def test_dominant_class_rule():
         "panel_qr": (170.0, 1e10, 1e9, 63),           # not a GEMM class
         "small_svd": (120.0, 0.0, 0.0, 1),            # not a GEMM class
         "splitk_reduce": (100.0, 1e9, 1e9, 40),       # not a GEMM class
-        "gemm_nn_fp64_t64": (90.0, 1e12, 1e9, 100),
+        "gemm_nn_fp64_t64_uv": (90.0, 1e12, 1e9, 100),
         "gemm_nt_fp64_t64": (30.0, 1e12, 1e9, 287),
         "gemm_nn_fp32_t128": (15.0, 1e12, 1e9, 46),
         "gemm_tn_bf16x3_t128": (400.0, 1e12, 1e9, 0),  # no launches: excluded
         "gemm_nn_bf16x3_t128": (4.0, 1e12, 1e9, 18),
     }
-    assert bench.dominant_class(prof) == "gemm_nn_fp64_t64"
+    assert bench.dominant_class(prof) == "gemm_nn_fp64_t64_uv"
     assert bench.dominant_class(prof, "bf16x3") == "gemm_nn_bf16x3_t128"
     assert bench.dominant_class(prof, "fp32") == "gemm_nn_fp32_t128"
 
@@ -48,7 +48,9 @@ def test_roofline_record_arithmetic():
     assert r["achieved"] == pytest.approx(50.0)
     assert r["frac"] == pytest.approx(50.0 / 78.6)
     assert r["avg_launch_us"] == pytest.approx(100.0)
-    assert r["kernel"] == "k_gemm<PREC_FP64, false, true, 128, 128, 2, 2>"
+    assert r["kernel"] == "k_gemm<PREC_FP64, false, true, 128, 128, 2, 2, 0>"
+    assert bench.kernel_symbol("gemm_nt_fp64_t64_uv") == \
+        "k_gemm<PREC_FP64, false, true, 64, 64, 2, 2, 2>"
     r = bench.roofline_of("gemm_tn_bf16x3_t128", prof, WORKLOAD)
     assert r["achieved"] == pytest.approx(500.0)
     assert r["frac"] == pytest.approx(1500.0 / 2500.0)
