@@ -155,13 +155,20 @@ def roofline_of(dom, prof_dom, workload):
     achieved = fl_k / (ms_k * 1e-3) / 1e12
     mfma_rate = BF16_PRODUCTS.get(arith, 1.0) * achieved
     rec = traffic_record(dom, workload, by_k / nl)
-    return {"bound": "mfma", "kernel": kernel_symbol(dom), "class": dom, "achieved": achieved,
-            "peak": PEAK_TFLOPS[arith], "unit": "TFLOP/s", "frac": mfma_rate / PEAK_TFLOPS[arith],
-            "traffic": rec["traffic_bytes_per_launch"] if rec else None,
-            "traffic_source": rec["file"] if rec else None,
-            "avg_launch_us": ms_k / nl * 1e3, "launches": nl, "flops_per_launch": fl_k / nl,
-            "algorithmic_bytes_per_launch": by_k / nl,
-            "algorithmic_gb_per_s": by_k / (ms_k * 1e-3) / 1e9}
+    out = {"bound": "mfma", "kernel": kernel_symbol(dom), "class": dom, "achieved": achieved,
+           "peak": PEAK_TFLOPS[arith], "unit": "TFLOP/s", "frac": mfma_rate / PEAK_TFLOPS[arith],
+           "traffic": rec["traffic_bytes_per_launch"] if rec else None,
+           "traffic_source": rec["file"] if rec else None,
+           "avg_launch_us": ms_k / nl * 1e3, "launches": nl, "flops_per_launch": fl_k / nl,
+           "algorithmic_bytes_per_launch": by_k / nl,
+           "algorithmic_gb_per_s": by_k / (ms_k * 1e-3) / 1e9}
+    alone = prof_dom.get(dom + "@alone")
+    if alone and alone[3] > 0:  # the same launches with nothing beside them
+        ms_a, fl_a, _, nl_a = alone
+        ach_a = fl_a / (ms_a * 1e-3) / 1e12
+        out.update({"avg_launch_us_alone": ms_a / nl_a * 1e3, "achieved_alone": ach_a,
+                    "frac_alone": BF16_PRODUCTS.get(arith, 1.0) * ach_a / PEAK_TFLOPS[arith]})
+    return out
 
 
 def run_path(B, torch, dA, dG, sig, m, n, b, q, prec, steps, warmup):
@@ -217,6 +224,18 @@ def run_path(B, torch, dA, dG, sig, m, n, b, q, prec, steps, warmup):
         B.randutv_status(work)
     log(f"[{prec}] dominant {dom}: {prof_dom[dom][0] / steps:.2f} ms/step over "
         f"{prof_dom[dom][3] // steps} launches/step")
+    # The dominant class's launches alone: the same factorizations with U
+    # and V on the main stream (RANDUTV_ONE_STREAM), so nothing runs beside
+    # them (the per-launch time a serializing profiler sees).
+    B.profile_begin(only=dom)
+    for _ in range(steps):
+        T.copy_(dA)
+        B.randutv_factor(T, dG, b, q, U=U, V=V, prec=prec, work=work, sync=False,
+                         one_stream=True)
+    torch.cuda.synchronize()
+    prof_dom[dom + "@alone"] = B.profile_end()[dom]
+    B.randutv_status(work)
+    log(f"[{prec}] dominant {dom} alone: {prof_dom[dom + '@alone'][0] / steps:.2f} ms/step")
     # Accuracy of this path's own outputs (outside the timed region).
     nA = torch.linalg.norm(dA).item()
     res = torch.linalg.norm(dA - U @ (T @ V.T)).item() / nA

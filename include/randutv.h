@@ -68,7 +68,10 @@ typedef enum {
 enum {
   RANDUTV_FORM_U = 1, /* accumulate U (m x m) */
   RANDUTV_FORM_V = 2, /* accumulate V (n x n) */
-  RANDUTV_ECON_U = 4  /* with FORM_U: only U's first min(m, n) columns (m x min(m, n)) */
+  RANDUTV_ECON_U = 4, /* with FORM_U: only U's first min(m, n) columns (m x min(m, n)) */
+  RANDUTV_ONE_STREAM = 8 /* U and V updated on `stream` itself, no second stream:
+                            slower, but every kernel runs alone on the device
+                            (for timing single kernels); same results */
 };
 
 /* Number of randomized steps of Figure "The algorithm randUTV": steps i
@@ -123,7 +126,8 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
  * 11  flags    RANDUTV_FORM_U | RANDUTV_FORM_V, and RANDUTV_ECON_U with
  *              FORM_U (the economy U is formed after the loop, from the left
  *              reflectors kept in its own columns, by backward accumulation;
- *              the full U by forward accumulation on a second stream).
+ *              the full U by forward accumulation on a second stream, or on
+ *              `stream` with RANDUTV_ONE_STREAM).
  * 12  work     device workspace of at least randutv_workspace_size() bytes,
  *              256-byte aligned.  Contents on entry are ignored.
  * 13  work_bytes

@@ -23,7 +23,7 @@ PREC = {"fp64": RANDUTV_FP64, "fp32": RANDUTV_FP32, "bf16x3": RANDUTV_BF16X3,
         "bf16x3_fp32": RANDUTV_BF16X3_FP32, "bf16x3_bf16x6": RANDUTV_BF16X3_BF16X6}
 # Arithmetic codes of randutv_gemm (a product has one arithmetic).
 GEMM_PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 4}
-FORM_U, FORM_V, ECON_U = 1, 2, 4
+FORM_U, FORM_V, ECON_U, ONE_STREAM = 1, 2, 4, 8
 
 _lib = None
 
@@ -225,7 +225,7 @@ def _aligned_ptr(ws):
 
 
 def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", work=None,
-                   sync=True, p=0):
+                   sync=True, p=0, one_stream=False):
     """In-place randUTV of T (m x n column-major FP64, overwritten by T).
 
     U (m x m, or m x min(m, n) for the economy form) and V (n x n) are
@@ -246,7 +246,7 @@ def randutv_factor(T, G, b, q, U=None, V=None, k_stop=0, tol=0.0, prec="fp64", w
     if U is not None and U.shape[1] not in (m, min(m, n)):
         raise RandUTVError("U must have m or min(m, n) columns")
     flags = (FORM_U if U is not None else 0) | (FORM_V if V is not None else 0) | \
-        (ECON_U if econ else 0)
+        (ECON_U if econ else 0) | (ONE_STREAM if one_stream else 0)
     need = workspace_size(m, n, b, q, prec, U is not None, V is not None, p=p, econ_u=econ)
     if work is None:
         work = workspace(need, T.device)

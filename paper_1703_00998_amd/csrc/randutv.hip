@@ -63,7 +63,8 @@ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // FORM_U, FORM_V, and ECON_U together with FORM_U.
 bool valid_flags(unsigned flags) {
-  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V | RANDUTV_ECON_U)) return false;
+  if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V | RANDUTV_ECON_U | RANDUTV_ONE_STREAM))
+    return false;
   return !(flags & RANDUTV_ECON_U) || (flags & RANDUTV_FORM_U);
 }
 
@@ -548,6 +549,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   if (formV) HIPCHK(set_identity(st, N, N, V, ldv));
   // Without the second stream (use_side false) U and V are updated on the
   // caller's stream, in the same launches.
+  if (flags & RANDUTV_ONE_STREAM) use_side = false;
   SideCtx* sc = (use_side && ((formU && !econU) || formV)) ? side_ctx() : nullptr;
   const hipStream_t ss = sc ? sc->side : st;  // U / V stream (the main one if none)
   bool vpend[kSlots] = {}, upend[kSlots] = {};

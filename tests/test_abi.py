@@ -70,7 +70,8 @@ def test_workspace_and_argument_validation(lib):
     # RANDUTV_ECON_U (4) only together with RANDUTV_FORM_U (1)
     assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 4, ctypes.byref(sz)) == -6
     assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 5, ctypes.byref(sz)) == 0
-    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 8, ctypes.byref(sz)) == -6
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 11, ctypes.byref(sz)) == 0  # ONE_STREAM
+    assert lib.randutv_workspace_size(100, 80, 16, 1, 0, 16, ctypes.byref(sz)) == -6
     vp = ctypes.c_void_p
     null = vp(0)
     fake = vp(1 << 20)  # never dereferenced: validation fails first
@@ -96,7 +97,8 @@ def test_workspace_and_argument_validation(lib):
     assert call(flags=1) == -6         # U requested but NULL
     assert call(flags=2) == -7
     assert call(prec=5) == -10
-    assert call(flags=8) == -11
+    assert call(flags=16) == -11
+    assert call(flags=4) == -11        # ECON_U without FORM_U
     assert call() == -12               # no workspace
     assert call(work=vp(4096 + 8)) == -12   # misaligned
     assert call(work=vp(4096), wb=16) == -901
@@ -122,7 +124,7 @@ def test_noalloc_entry_point_validates(lib):
     assert call(flags=1) == -6
     assert call(flags=2) == -7
     assert call(prec=5) == -10
-    assert call(flags=8) == -11
+    assert call(flags=16) == -11
     # 4000 x 4000, b = 256 with U and V needs more than the 128 MiB array.
     assert call(m=4000, n=4000, b=256, ldt=4000, U=fake, V=fake, flags=3) == -901
 

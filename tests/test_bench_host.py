@@ -51,6 +51,11 @@ def test_roofline_record_arithmetic():
     assert r["kernel"] == "k_gemm<PREC_FP64, false, true, 128, 128, 2, 2, 0>"
     assert bench.kernel_symbol("gemm_nt_fp64_t64_uv") == \
         "k_gemm<PREC_FP64, false, true, 64, 64, 2, 2, 2>"
+    prof["gemm_nt_fp64_t128@alone"] = (5.0, 5e11, 2e9, 100)
+    r = bench.roofline_of("gemm_nt_fp64_t128", prof, WORKLOAD)
+    assert r["achieved_alone"] == pytest.approx(100.0)
+    assert r["frac_alone"] == pytest.approx(100.0 / 78.6)
+    assert r["avg_launch_us_alone"] == pytest.approx(50.0)
     r = bench.roofline_of("gemm_tn_bf16x3_t128", prof, WORKLOAD)
     assert r["achieved"] == pytest.approx(500.0)
     assert r["frac"] == pytest.approx(1500.0 / 2500.0)

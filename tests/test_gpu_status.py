@@ -96,3 +96,27 @@ def test_status_of_an_unused_workspace(B):
     work = torch.zeros(4096, dtype=torch.uint8, device="cuda")
     st, _ = B.randutv_status(work, raise_on_error=False)
     assert st == E_UNSUPPORTED
+
+
+def test_one_stream_flag_gives_the_same_factors(B):
+    """RANDUTV_ONE_STREAM (U and V on the caller's stream, no second stream)
+    runs the same kernels on the same data in the same order per buffer, so
+    T, U and V equal the two-stream result bit for bit; both match the
+    oracle."""
+    from oracle import randutv_ref as ref
+    from paper_1703_00998_amd import workloads as wl
+    m, n, b, q = 600, 520, 64, 1
+    A, G = _case(wl, m, n, b, 3)
+    dG = B.colmajor(G)
+    out = []
+    for one in (False, True):
+        T = B.colmajor(A)
+        U, V = B.empty_colmajor(m, m), B.empty_colmajor(n, n)
+        k = B.randutv_factor(T, dG, b, q, U=U, V=V, one_stream=one)
+        assert k == n
+        out.append([x.cpu().numpy() for x in (T, U, V)])
+    for x2, x1 in zip(*out):
+        assert np.array_equal(x2, x1)
+    Uo, To, Vo, _ = ref.randutv(A, b, q, G)
+    for got, want in zip(out[1], (To, Uo, Vo)):
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-10)
