@@ -44,12 +44,26 @@ namespace {
 
 constexpr int MAXN = 1024;
 constexpr int kBW = 16;          // Jacobi block width
-constexpr int kRoundThreads = 16 * kBW;  // a 16-lane row for each of the kBW pairs of a sub-round
+// Lanes per column pair in a round: 16 (one DPP row), the kBW pairs of a
+// sub-round on four waves, one per SIMD.  (32 lanes, two DPP rows and eight
+// waves so that two per SIMD overlap their latencies, measured the same:
+// 31-39 us per round of 256-row blocks either way.)
+#ifndef JACOBI_LPP
+#define JACOBI_LPP 16
+#endif
+constexpr int kLPP = JACOBI_LPP;
+constexpr int kRoundThreads = kLPP * kBW;
 constexpr int kMaxLdsN = 256;    // largest order handled by the LDS block kernel
 // Sweeps run as block rounds (a launch per round); the rest of the budget,
 // needed only by matrices not converged by then, runs in one launch.  The
 // factorization's b x b blocks take about 11 sweeps.
 constexpr int kBlockSweeps = 14;
+// LDS column stride of a round, in doubles: 16 rows per lane-row chunk plus
+// a pad (see k_bj_round).
+#ifndef JACOBI_LDS_PAD
+#define JACOBI_LDS_PAD 1
+#endif
+constexpr int lds_stride(int nt) { return kLPP * nt + JACOBI_LDS_PAD; }
 
 // DPP move of a double (two 32-bit halves) with control CTRL.
 template <int CTRL>
@@ -304,11 +318,19 @@ __global__ void k_bj_init(const int* __restrict__ nbs, int ld, const double* __r
     for (int s = threadIdx.x; s < max_sweeps; s += blockDim.x) rotcount[mi * max_sweeps + s] = 0;
 }
 
-// Rows i = l16 + 16 t (t < NT) of two columns x, y held in registers,
+// Sum over the kLPP lanes of a pair (one or two DPP rows), in every lane
+// of the pair.  Called with all lanes active.
+__device__ inline double pair_sum(double v) {
+  v = row_sum(v);
+  if (kLPP == 32) v += __shfl_xor(v, 16, 64);
+  return v;
+}
+
+// Rows i = lp + kLPP t (t < NT) of two columns x, y held in registers,
 // rotated by the Jacobi rotation of the pair when `ok` and they are not
 // orthogonal to tolerance; otherwise (c, s) = (1, 0) leaves them exactly as
-// they are, so the code has no branch.  One 16-lane row per pair; every
-// lane of the wave calls it (the row sums use DPP).
+// they are, so the code has no branch.  kLPP lanes per pair; every lane of
+// the wave calls it (the sums use DPP).
 template <int NT>
 __device__ inline bool rotate_regs(double (&xw)[NT], double (&xv)[NT], double (&yw)[NT],
                                    double (&yv)[NT], double tol, bool ok) {
@@ -319,9 +341,9 @@ __device__ inline bool rotate_regs(double (&xw)[NT], double (&xv)[NT], double (&
     be += yw[t] * yw[t];
     ga += xw[t] * yw[t];
   }
-  al = row_sum(al);
-  be = row_sum(be);
-  ga = row_sum(ga);
+  al = pair_sum(al);
+  be = pair_sum(be);
+  ga = pair_sum(ga);
   double c = 1.0, s = 0.0;
   const bool rot = ok && jacobi_cs(al, be, ga, tol, &c, &s);
   if (!rot) c = 1.0, s = 0.0;
@@ -337,21 +359,21 @@ __device__ inline bool rotate_regs(double (&xw)[NT], double (&xv)[NT], double (&
   return rot;
 }
 
-// A column of the LDS block: rows l16 + 16 t; the rows from nb to 16 NT
+// A column of the LDS block: rows lp + kLPP t; the rows from nb to kLPP NT
 // hold zeros, which rotations keep.
 template <int NT>
-__device__ inline void lds_col_load(double (&r)[NT], const double* col, int l16) {
+__device__ inline void lds_col_load(double (&r)[NT], const double* col, int lp) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) r[t] = col[l16 + 16 * t];
+  for (int t = 0; t < NT; ++t) r[t] = col[lp + kLPP * t];
 }
 template <int NT>
-__device__ inline void lds_col_store(const double (&r)[NT], double* col, int l16) {
+__device__ inline void lds_col_store(const double (&r)[NT], double* col, int lp) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) col[l16 + 16 * t] = r[t];
+  for (int t = 0; t < NT; ++t) col[lp + kLPP * t] = r[t];
 }
 
 // One round of the block tournament: every column pair across blocks bp and
-// bq (and in round 0 the pairs inside each of them).  NT = ceil(ld / 16)
+// bq (and in round 0 the pairs inside each of them).  NT = ceil(ld / kLPP)
 // rows per lane.
 template <int NT>
 __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restrict__ nbs, int ld,
@@ -367,11 +389,12 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
   if (sweep > 0 && rotcount[mi * max_sweeps + sweep - 1] == 0) return;  // converged
   int bp, bq;
   rr_pair(nblk2, round, pi, &bp, &bq);
-  constexpr int ldl = 16 * NT + 1;  // LDS column stride: 16 NT rows, odd
+  constexpr int ldl = lds_stride(NT);  // LDS column stride: kLPP NT rows and the pad
   double* sW = sm;
   double* sV = sm + 2 * kBW * ldl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int slot = wave * 4 + (lane >> 4), l16 = lane & 15;  // pair index, lane in the row
+  const int slot = tid / kLPP, lp = tid % kLPP;  // pair index, lane in the pair
+  constexpr int kWaves = kRoundThreads / 64;
   double* W = Wk + mi * strideUV;
   double* V = Vk + mi * strideUV;
   auto gcol = [&](int c) -> int {  // global column of local column c, or -1
@@ -379,16 +402,16 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
     const int g = blk * kBW + (c % kBW);
     return (blk < nblk && g < nb) ? g : -1;
   };
-  // Wave w loads columns w, w + 4, ... of the pair, rows lane + 64 u, and
-  // issues every load before its first LDS store: with one workgroup per CU
-  // the round is otherwise bound by the latency of these loads.
-  constexpr int NU = (NT + 3) / 4;  // 64-row chunks per column
-  constexpr int kCols = 2 * kBW / (kRoundThreads / 64);
+  // Wave w loads columns w, w + kWaves, ... of the pair, rows lane + 64 u,
+  // and issues every load before its first LDS store: with one workgroup
+  // per CU the round is otherwise bound by the latency of these loads.
+  constexpr int NU = (kLPP * NT + 63) / 64;  // 64-row chunks per column
+  constexpr int kCols = 2 * kBW / kWaves;
   {
     double lw[kCols][NU], lv[kCols][NU];
 #pragma unroll
     for (int v = 0; v < kCols; ++v) {
-      const int g = gcol(wave + 4 * v);
+      const int g = gcol(wave + kWaves * v);
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
         const int i = lane + 64 * u;
@@ -399,11 +422,11 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
     }
 #pragma unroll
     for (int v = 0; v < kCols; ++v) {
-      const int c = wave + 4 * v;
+      const int c = wave + kWaves * v;
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
         const int i = lane + 64 * u;
-        if (i < 16 * NT) {  // zeros from row nb on
+        if (i < kLPP * NT) {  // zeros from row nb on
           sW[c * ldl + i] = lw[v][u];
           sV[c * ldl + i] = lv[v][u];
         }
@@ -424,15 +447,15 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
       rr_pair(kBW, r, kk, &p, &q);
       p += half * kBW;
       q += half * kBW;
-      lds_col_load(xw, sW + p * ldl, l16);
-      lds_col_load(xv, sV + p * ldl, l16);
-      lds_col_load(yw, sW + q * ldl, l16);
-      lds_col_load(yv, sV + q * ldl, l16);
+      lds_col_load(xw, sW + p * ldl, lp);
+      lds_col_load(xv, sV + p * ldl, lp);
+      lds_col_load(yw, sW + q * ldl, lp);
+      lds_col_load(yv, sV + q * ldl, lp);
       rot |= rotate_regs(xw, xv, yw, yv, tol, gcol(p) >= 0 && gcol(q) >= 0);
-      lds_col_store(xw, sW + p * ldl, l16);
-      lds_col_store(xv, sV + p * ldl, l16);
-      lds_col_store(yw, sW + q * ldl, l16);
-      lds_col_store(yv, sV + q * ldl, l16);
+      lds_col_store(xw, sW + p * ldl, lp);
+      lds_col_store(xv, sV + p * ldl, lp);
+      lds_col_store(yw, sW + q * ldl, lp);
+      lds_col_store(yv, sV + q * ldl, lp);
       __syncthreads();
     }
   }
@@ -441,15 +464,15 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
   // registers throughout; the columns of block bq move through LDS.
   const int p = slot;
   const bool okp = gcol(p) >= 0;
-  lds_col_load(xw, sW + p * ldl, l16);
-  lds_col_load(xv, sV + p * ldl, l16);
+  lds_col_load(xw, sW + p * ldl, lp);
+  lds_col_load(xv, sV + p * ldl, lp);
   for (int r = 0; r < kBW; ++r) {
     const int q = kBW + (slot + r) % kBW;
-    lds_col_load(yw, sW + q * ldl, l16);
-    lds_col_load(yv, sV + q * ldl, l16);
+    lds_col_load(yw, sW + q * ldl, lp);
+    lds_col_load(yv, sV + q * ldl, lp);
     rot |= rotate_regs(xw, xv, yw, yv, tol, okp && gcol(q) >= 0);
-    lds_col_store(yw, sW + q * ldl, l16);
-    lds_col_store(yv, sV + q * ldl, l16);
+    lds_col_store(yw, sW + q * ldl, lp);
+    lds_col_store(yv, sV + q * ldl, lp);
     __syncthreads();
   }
   // Block bp's columns from registers, block bq's from LDS.
@@ -457,14 +480,14 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
     const int g = gcol(p);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int i = l16 + 16 * t;
+      const int i = lp + kLPP * t;
       if (i < nb) {
         W[i + (int64_t)g * ld] = xw[t];
         V[i + (int64_t)g * ld] = xv[t];
       }
     }
   }
-  for (int c = kBW + wave; c < 2 * kBW; c += kRoundThreads / 64) {
+  for (int c = kBW + wave; c < 2 * kBW; c += kWaves) {
     const int g = gcol(c);
     if (g < 0) continue;
     for (int i = lane; i < nb; i += 64) {
@@ -616,19 +639,19 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
     return hipGetLastError();
   }
   static bool attr_set = false;
-  constexpr int kMaxNT = kMaxLdsN / 16;
+  constexpr int kMaxNT = kMaxLdsN / kLPP;
   // LDS of a round: W and V columns of two blocks, 16 NT + 1 rows each.
-  const size_t shmem = (size_t)4 * kBW * (16 * ((ld + 15) / 16) + 1) * sizeof(double);
+  const size_t shmem = (size_t)4 * kBW * lds_stride((ld + kLPP - 1) / kLPP) * sizeof(double);
   const auto nts = std::make_integer_sequence<int, kMaxNT>();
   if (!attr_set) {
     for (int nt = 1; nt <= kMaxNT; ++nt)
       (void)hipFuncSetAttribute((const void*)round_fn(nt, nts),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)((size_t)4 * kBW * (kMaxLdsN | 1) * sizeof(double)));
+                                (int)((size_t)4 * kBW * lds_stride(kMaxNT) * sizeof(double)));
     (void)hipGetLastError();
     attr_set = true;
   }
-  const RoundFn round = round_fn((ld + 15) / 16, nts);
+  const RoundFn round = round_fn((ld + kLPP - 1) / kLPP, nts);
   // Per-matrix sweep counters follow the status words: count * max_sweeps ints.
   int* rotcount = status + count;
   hipLaunchKernelGGL(k_bj_init, dim3(16, count), dim3(256), 0, st, nb_dev, ld, R, strideR, Wk, Vk,
