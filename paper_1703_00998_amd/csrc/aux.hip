@@ -5,6 +5,9 @@
 // the status words a call leaves in its workspace.
 // All of them are HBM-bound single passes over column-major data.
 #include <algorithm>
+#include <mutex>
+#include <set>
+#include <utility>
 
 #include "../../include/randutv.h"
 #include "common.h"
@@ -163,6 +166,19 @@ int read_status(const void* work, int64_t* k_out, hipStream_t st) {
   if (k_out) *k_out = h.k;
   if (h.sync_err) return RANDUTV_E_SYNC;
   return h.svd_fail ? 1 : 0;
+}
+
+hipError_t ensure_dyn_lds(const void* fn, int bytes) {
+  static std::mutex mu;
+  static std::set<std::pair<int, const void*>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count({dev, fn})) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done.insert({dev, fn});
+  return e;
 }
 
 }  // namespace rutv

@@ -175,6 +175,10 @@ hipError_t status_done(hipStream_t st, StatusBlock* blk, long long k);
 // when no call has completed there) and *k_out (may be NULL).
 int read_status(const void* work, int64_t* k_out, hipStream_t st);
 
+// Raises kernel `fn`'s dynamic-LDS limit to `bytes` on the current device,
+// once per device and kernel (thread-safe).
+hipError_t ensure_dyn_lds(const void* fn, int bytes);
+
 // ---------------------------------------------------------------- factor core
 // Reflectors and R factors of the first t steps, for the truncated
 // approximation and its backward: per step i, Vy (n x b, ld n), Ty and Ry

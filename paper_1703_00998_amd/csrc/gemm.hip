@@ -172,20 +172,48 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
   // slower).
   using LoadT = double;
   LoadT ra[LA], rb[LB];
+  // Slabs that lie wholly inside A (or B) take a path without per-element
+  // guards: element r sits at a fixed offset from the thread's first one
+  // (r * rsA, resp. r * rsB), and a slab moves by k0 * ksA (ksB).  The guards
+  // compile to exec-mask branches around every load and keep the compiler
+  // from interleaving the loads with the MFMAs.
+  int a_i0, a_k0, b_k0, b_j0;
+  a_idx(0, a_i0, a_k0);
+  b_idx(0, b_k0, b_j0);
+  const int64_t offA = TA ? a_k0 + (int64_t)(m0 + a_i0) * lda : (m0 + a_i0) + (int64_t)a_k0 * lda;
+  const int64_t rsA = TA ? (int64_t)(NT / BK) * lda : (int64_t)(NT / BM) * lda;
+  const int64_t ksA = TA ? 1 : lda;
+  const int64_t offB = TB ? (n0 + b_j0) + (int64_t)b_k0 * ldb : b_k0 + (int64_t)(n0 + b_j0) * ldb;
+  const int64_t rsB = TB ? (int64_t)(NT / BN) * ldb : (int64_t)(NT / BK) * ldb;
+  const int64_t ksB = TB ? ldb : 1;
+  const bool rowsA = m0 + BM <= M, colsB = n0 + BN <= N;
   auto load = [&](int k0) {
+    const bool kin = k0 + BK <= kend;
+    if (rowsA && kin) {
+      const double* pa = A + offA + (int64_t)k0 * ksA;
 #pragma unroll
-    for (int r = 0; r < LA; ++r) {
-      int i, k;
-      a_idx(r, i, k);
-      const int gi = m0 + i, gk = k0 + k;
-      ra[r] = (gi < M && gk < kend) ? (TA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
+      for (int r = 0; r < LA; ++r) ra[r] = pa[r * rsA];
+    } else {
+#pragma unroll
+      for (int r = 0; r < LA; ++r) {
+        int i, k;
+        a_idx(r, i, k);
+        const int gi = m0 + i, gk = k0 + k;
+        ra[r] = (gi < M && gk < kend) ? (TA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
+      }
     }
+    if (colsB && kin) {
+      const double* pb = B + offB + (int64_t)k0 * ksB;
 #pragma unroll
-    for (int r = 0; r < LB; ++r) {
-      int k, j;
-      b_idx(r, k, j);
-      const int gj = n0 + j, gk = k0 + k;
-      rb[r] = (gj < N && gk < kend) ? (TB ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb]) : 0.0;
+      for (int r = 0; r < LB; ++r) rb[r] = pb[r * rsB];
+    } else {
+#pragma unroll
+      for (int r = 0; r < LB; ++r) {
+        int k, j;
+        b_idx(r, k, j);
+        const int gj = n0 + j, gk = k0 + k;
+        rb[r] = (gj < N && gk < kend) ? (TB ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb]) : 0.0;
+      }
     }
   };
   auto store = [&](int buf) {

@@ -924,22 +924,15 @@ hipError_t panel_qr(hipStream_t st, int Mp, int nb, double* P, int64_t ldp, doub
                     double* Tw, int64_t ldtw, const PanelWork& w, const int* gate) {
   if (nb <= 0) return hipSuccess;
   if (nb > MAXB || Mp < nb) return hipErrorInvalidValue;
-  static int cu_count = 0;
-  static int kLdsBytes = 0;
-  static bool attr_set = false;
-  if (!cu_count) {
-    int dev = 0, lds = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cu_count = 1;
-    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      lds = 64 * 1024;
-    kLdsBytes = std::min(lds, 160 * 1024);
-    if (hipFuncSetAttribute((const void*)k_panel_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsBytes) == hipSuccess)
-      attr_set = true;
-    (void)hipGetLastError();
-  }
+  int dev = 0, cu_count = 1, lds = 64 * 1024;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cu_count, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cu_count = 1;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    lds = 64 * 1024;
+  const int kLdsBytes = std::min(lds, 160 * 1024);
+  const bool attr_set = ensure_dyn_lds((const void*)k_panel_lds, kLdsBytes) == hipSuccess;
+  (void)hipGetLastError();
   // LDS-resident variant: slab of `chunk` rows x nb columns per workgroup.
   const int fixed = kFixedLdsDoubles(nb);
   const int max_ld = (kLdsBytes / 8 - fixed) / (nb + PNB);

@@ -638,20 +638,15 @@ hipError_t batched_svd(hipStream_t st, int count, const int* nb_dev, int ld, con
     prof_done(st, slot, PC_SVD, 0.0, 0.0);
     return hipGetLastError();
   }
-  static bool attr_set = false;
   constexpr int kMaxNT = kMaxLdsN / kLPP;
-  // LDS of a round: W and V columns of two blocks, 16 NT + 1 rows each.
-  const size_t shmem = (size_t)4 * kBW * lds_stride((ld + kLPP - 1) / kLPP) * sizeof(double);
-  const auto nts = std::make_integer_sequence<int, kMaxNT>();
-  if (!attr_set) {
-    for (int nt = 1; nt <= kMaxNT; ++nt)
-      (void)hipFuncSetAttribute((const void*)round_fn(nt, nts),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)((size_t)4 * kBW * lds_stride(kMaxNT) * sizeof(double)));
-    (void)hipGetLastError();
-    attr_set = true;
+  // LDS of a round: W and V columns of two blocks, lds_stride(NT) rows each.
+  const int nt = (ld + kLPP - 1) / kLPP;
+  const size_t shmem = (size_t)4 * kBW * lds_stride(nt) * sizeof(double);
+  const RoundFn round = round_fn(nt, std::make_integer_sequence<int, kMaxNT>());
+  {
+    const hipError_t e = ensure_dyn_lds((const void*)round, (int)shmem);
+    if (e != hipSuccess) return e;
   }
-  const RoundFn round = round_fn((ld + kLPP - 1) / kLPP, nts);
   // Per-matrix sweep counters follow the status words: count * max_sweeps ints.
   int* rotcount = status + count;
   hipLaunchKernelGGL(k_bj_init, dim3(16, count), dim3(256), 0, st, nb_dev, ld, R, strideR, Wk, Vk,
