@@ -140,8 +140,9 @@ def kernel_symbol(cls):
     parts = cls.split("_")
     _, op, arith, tile = parts[:4]
     role = 2 if parts[4:] == ["uv"] else 0
+    waves = "2, 4" if (arith, tile) == ("fp64", "t128") else "2, 2"  # FP64 128 x 128: 2 x 4 waves
     return (f"k_gemm<PREC_{arith.upper()}, {'true' if op[0] == 't' else 'false'}, "
-            f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, 2, 2, {role}>")
+            f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, {waves}, {role}>")
 
 
 def roofline_of(dom, prof_dom, workload):

@@ -118,7 +118,7 @@ __device__ inline Bf3 split3(float x32) {
 // products inside the Householder panel factorizations, 2 for the U / V
 // stream's products.
 template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN, int ROLE>
-__global__ __launch_bounds__(64 * WM * WN, WM * WN == 4 ? 2 : 1) void k_gemm(
+__global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
     int M, int N, int K, int kper, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double* __restrict__ C, int64_t ldc,
     int64_t zstride, double alpha, double beta) {
@@ -517,12 +517,17 @@ void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, 
   else launch<P, true, true, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 
-// Tile shapes: 0 = 64 x 64, 1 = 128 x 128, both on 2 x 2 waves.
+// Tile shapes: 0 = 64 x 64 on 2 x 2 waves; 1 = 128 x 128 on 2 x 2 waves, in
+// FP64 on 2 x 4 waves of 64 x 32 (two workgroups of eight waves per CU, four
+// waves per SIMD to cover each other's LDS and barrier waits: 50-61 against
+// 47-58 TFLOP/s on the 8000 x 8000 thin products alone; 4 x 2 waves of
+// 32 x 64 need 140 registers, one workgroup per CU, and were slower).
 template <int P, int ROLE = 0>
 void launch_p(hipStream_t st, int shape, bool ta, bool tb, dim3 grid, int M, int N, int K,
               int kper, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
               int64_t ldc, int64_t zs, double al, double be) {
-  if (shape == 1) launch_t<P, 128, 128, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  if (shape == 1 && P == PREC_FP64) launch_t<P, 128, 128, 2, 4, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+  else if (shape == 1) launch_t<P, 128, 128, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
   else launch_t<P, 64, 64, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
 }
 

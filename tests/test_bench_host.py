@@ -48,7 +48,7 @@ def test_roofline_record_arithmetic():
     assert r["achieved"] == pytest.approx(50.0)
     assert r["frac"] == pytest.approx(50.0 / 78.6)
     assert r["avg_launch_us"] == pytest.approx(100.0)
-    assert r["kernel"] == "k_gemm<PREC_FP64, false, true, 128, 128, 2, 2, 0>"
+    assert r["kernel"] == "k_gemm<PREC_FP64, false, true, 128, 128, 2, 4, 0>"
     assert bench.kernel_symbol("gemm_nt_fp64_t64_uv") == \
         "k_gemm<PREC_FP64, false, true, 64, 64, 2, 2, 2>"
     prof["gemm_nt_fp64_t128@alone"] = (5.0, 5e11, 2e9, 100)
