@@ -21,7 +21,8 @@
 // pairs per wave, the kBW pairs of a sub-round on four waves, one per
 // SIMD), so the scalar rotation arithmetic of four pairs shares each
 // instruction, and in the cross sub-rounds a row keeps its block-bp column
-// in registers while the block-bq columns pass through LDS.  Blocks stay in
+// in registers while the block-bq columns move between rows, by lane
+// shuffles inside a wave and through LDS between waves.  Blocks stay in
 // place in global memory, so
 // the kernel boundary between rounds is the only synchronization.  A sweep
 // is nblk-1 rounds; the SVDs of all randUTV steps advance together (grid.y
@@ -372,6 +373,24 @@ __device__ inline void lds_col_store(const double (&r)[NT], double* col, int lp)
   for (int t = 0; t < NT; ++t) col[lp + kLPP * t] = r[t];
 }
 
+// Binary reflected Gray code: gray(r) and gray(r + 1) differ in one bit.
+__device__ constexpr int gray(int r) { return r ^ (r >> 1); }
+// How many of the moves before sub-round r + 1 cross waves (the moves whose
+// bit is at least 64 / kLPP slots), counting the one after sub-round r.
+__device__ constexpr int cross_move_index(int r) {
+  int c = 0;
+  for (int i = 0; i < r; ++i)
+    if ((gray(i) ^ gray(i + 1)) * kLPP >= 64) ++c;
+  return c;
+}
+// Exchange a register column with the lanes LANES apart (16 or 32: the
+// other DPP row of a row pair, or the other half of the wave).
+template <int LANES, int NT>
+__device__ inline void swap_rows(double (&r)[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) r[t] = __shfl_xor(r[t], LANES, 64);
+}
+
 // One round of the block tournament: every column pair across blocks bp and
 // bq (and in round 0 the pairs inside each of them).  NT = ceil(ld / kLPP)
 // rows per lane.
@@ -459,40 +478,63 @@ __global__ __launch_bounds__(kRoundThreads) void k_bj_round(const int* __restric
       __syncthreads();
     }
   }
-  // Cross pairs (p in block bp, q in block bq): kBW sub-rounds of kBW
-  // disjoint pairs (k, kBW + (k + r) mod kBW).  Row k keeps column k in
-  // registers throughout; the columns of block bq move through LDS.
+  // Cross pairs (column p of block bp, column j of block bq): kBW
+  // sub-rounds; in sub-round r the pair slot p, which keeps column p of bp
+  // in registers throughout, meets column j = p ^ gray(r) of bq, so over the
+  // kBW sub-rounds it meets every column of bq once.  Between sub-rounds r
+  // and r + 1 the bq columns move from slot p ^ m to slot p, m = gray(r) ^
+  // gray(r + 1) a single bit: for m = 1 and 2 the two slots are DPP rows of
+  // one wave (lanes ^ 16, ^ 32) and the columns cross by lane shuffles; for
+  // m = 4 and 8 (three of the kBW - 1 moves) they cross waves through LDS.
   const int p = slot;
   const bool okp = gcol(p) >= 0;
   lds_col_load(xw, sW + p * ldl, lp);
   lds_col_load(xv, sV + p * ldl, lp);
+  lds_col_load(yw, sW + (kBW + p) * ldl, lp);
+  lds_col_load(yv, sV + (kBW + p) * ldl, lp);
+  __syncthreads();  // every slot holds its columns before LDS is written again
+#pragma unroll
   for (int r = 0; r < kBW; ++r) {
-    const int q = kBW + (slot + r) % kBW;
-    lds_col_load(yw, sW + q * ldl, lp);
-    lds_col_load(yv, sV + q * ldl, lp);
-    rot |= rotate_regs(xw, xv, yw, yv, tol, okp && gcol(q) >= 0);
-    lds_col_store(yw, sW + q * ldl, lp);
-    lds_col_store(yv, sV + q * ldl, lp);
-    __syncthreads();
+    const int j = p ^ gray(r);
+    rot |= rotate_regs(xw, xv, yw, yv, tol, okp && gcol(kBW + j) >= 0);
+    if (r + 1 == kBW) break;
+    const int m = gray(r) ^ gray(r + 1);
+    if (m * kLPP == 16) {
+      swap_rows<16>(yw);
+      swap_rows<16>(yv);
+    } else if (m * kLPP == 32) {
+      swap_rows<32>(yw);
+      swap_rows<32>(yv);
+    } else {
+      // The LDS moves alternate between the halves of the block buffers (bq's
+      // first, then bp's, whose columns are in registers by now), so a move
+      // never writes where the previous one may still be read.
+      const int half = (cross_move_index(r) & 1) ? 0 : kBW;
+      lds_col_store(yw, sW + (half + j) * ldl, lp);
+      lds_col_store(yv, sV + (half + j) * ldl, lp);
+      __syncthreads();
+      const int jn = p ^ gray(r + 1);
+      lds_col_load(yw, sW + (half + jn) * ldl, lp);
+      lds_col_load(yv, sV + (half + jn) * ldl, lp);
+    }
   }
-  // Block bp's columns from registers, block bq's from LDS.
-  if (okp) {
-    const int g = gcol(p);
+  // Both columns of each slot go back from registers: column p of bp and
+  // column p ^ gray(kBW - 1) of bq.
+  {
+    const int gp = gcol(p), gq = gcol(kBW + (p ^ gray(kBW - 1)));
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int i = lp + kLPP * t;
       if (i < nb) {
-        W[i + (int64_t)g * ld] = xw[t];
-        V[i + (int64_t)g * ld] = xv[t];
+        if (gp >= 0) {
+          W[i + (int64_t)gp * ld] = xw[t];
+          V[i + (int64_t)gp * ld] = xv[t];
+        }
+        if (gq >= 0) {
+          W[i + (int64_t)gq * ld] = yw[t];
+          V[i + (int64_t)gq * ld] = yv[t];
+        }
       }
-    }
-  }
-  for (int c = kBW + wave; c < 2 * kBW; c += kWaves) {
-    const int g = gcol(c);
-    if (g < 0) continue;
-    for (int i = lane; i < nb; i += 64) {
-      W[i + (int64_t)g * ld] = sW[c * ldl + i];
-      V[i + (int64_t)g * ld] = sV[c * ldl + i];
     }
   }
   if (__syncthreads_or(rot) && tid == 0) atomicAdd(&rotcount[mi * max_sweeps + sweep], 1);
