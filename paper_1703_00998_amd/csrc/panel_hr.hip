@@ -37,6 +37,9 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kBlk = 128;      // widest block factored in LDS (wider panels: two blocks)
 constexpr int LDA = kBlk + 1;  // LDS leading dimension (odd: spreads the banks)
 constexpr int kLoadCols = kThreads / kBlk;  // columns per pass when loading a block
+// Largest max |G - I| for which the second CholeskyQR pass takes its factors
+// from the first-order expansion (see k_hr_chol): 128 (2^-30)^2 = 2^-53.
+constexpr double kNearIdentity = 0x1p-30;
 
 __device__ inline v4d mfma(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -578,6 +581,12 @@ __device__ void inv_unit_lower_lds(Smem& sm, int nt) {
 //           beyond about 3e6, where CholeskyQR2 loses orthogonality);
 //   pass 2: fail unless max |G - I| < 0.1 (the first pass was accurate
 //           enough for the second to reach orthogonality to rounding).
+//           When max |G - I| <= 2^-30 (any panel with kappa up to about
+//           1e4), G = I + E and the factors are taken from the expansion
+//           R = I + N + D/2, R^-1 = I - N - D/2 (N the strictly upper part
+//           of E, D its diagonal), whose neglected terms are at most
+//           n max|E|^2 <= 2^-53 in each entry: rounding level, without the
+//           sequential factorization.
 // flag: stores the verdict if `overwrite`, else ORs into it.
 __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const double* __restrict__ G,
                                                       int ldg, double* __restrict__ R,
@@ -625,6 +634,19 @@ __global__ __launch_bounds__(kThreads) void k_hr_chol(int n, int nt, const doubl
     thr = 0.5;
   }
   __syncthreads();
+  if (pass == 2 && gm <= kNearIdentity) {
+    for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
+      const int idx = i + j * nbp;
+      const double e = sm.A[i + j * LDA] - (i == j ? 1.0 : 0.0);
+      R[idx] = i < j ? e : (i == j ? 1.0 + 0.5 * e : 0.0);
+      Ri[idx] = i < j ? -e : (i == j ? 1.0 - 0.5 * e : 0.0);
+    }
+    if (tid == 0) {
+      if (overwrite) *flag = sm.fail;
+      else if (sm.fail) *flag = 1;
+    }
+    return;
+  }
   chol_inv_lds(sm, n, nt, thr, R);
   for (int j = elem_j0(nbp), i = (tid) % nbp; j < nbp; j += kThreads / nbp) {
     const int idx = i + j * nbp;
