@@ -611,6 +611,27 @@ def approx_run(B, torch, wl):
         return {"error": repr(e)}
 
 
+def sampling_gemm_study(B, torch, reps=3):
+    """The first step's sampling product Y = X^T G of the 8000 x 8000, b = 256
+    workload (Section 5.4's application of A to a thin matrix) alone, in
+    BF16x3 and in FP64, `reps` launches each after one warm-up, with split-K
+    as the factorization runs it: a short program for counter passes."""
+    M, N, K = 8000, 256, 8000
+    gen = torch.Generator(device="cuda").manual_seed(1)
+    X = torch.randn((K, M), dtype=torch.float64, device="cuda", generator=gen)
+    G = torch.randn((K, N), dtype=torch.float64, device="cuda", generator=gen)
+    Xc, Gc = X.T.contiguous().T, G.T.contiguous().T  # column-major
+    Y = torch.zeros((N, M), dtype=torch.float64, device="cuda").T
+    ws = B.workspace(8 * M * N * 8)
+    out = {}
+    for prec in ("bf16x3", "fp64"):
+        run = lambda: B.randutv_gemm(Y, Xc, Gc, ta=True, tb=False, prec=prec, work=ws)
+        ms = _timed(torch, run, reps)
+        out[prec] = {"ms": ms, "tflops": 2.0 * M * N * K / (ms * 1e-3) / 1e12}
+        log(f"sampling product {prec}: {ms:.3f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -626,9 +647,11 @@ def main():
     ap.add_argument("--extra", default="q2,early_stop,approx,wide,oversample,rsvd,lower",
                     help="which extra workloads to time (comma-separated)")
     ap.add_argument("--cpu-n", type=int, default=1024)
-    ap.add_argument("--study", choices=["accuracy"],
+    ap.add_argument("--study", choices=["accuracy", "gemm"],
                     help="instead of the timing line, run the rank-k accuracy study of "
-                         "Section 6.2 (4000 x 4000, b = 100, q = 0, 1, 2) and print its JSON")
+                         "Section 6.2 (4000 x 4000, b = 100, q = 0, 1, 2), or time the "
+                         "8000 x 8000 workload's sampling product alone in BF16x3 and "
+                         "FP64 (gemm), and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -649,6 +672,10 @@ def main():
     if args.study == "accuracy":
         print(json.dumps({"study": "rank-k accuracy (Section 6.2)",
                           **accuracy_study(B, torch, wl)}), flush=True)
+        return
+    if args.study == "gemm":
+        print(json.dumps({"study": "sampling product X^T G, 8000 x 8000 by 8000 x 256",
+                          **sampling_gemm_study(B, torch)}), flush=True)
         return
     cfg = wl.CONFIGS["c3_8000"]
     m, n, b, q = cfg["m"], cfg["n"], cfg["b"], args.q
