@@ -69,10 +69,32 @@ void prof_done(hipStream_t st, int slot, int cls, double flops, double bytes);
 // by `prec`; operands and C are FP64 in memory.
 // small_tiles marks the U / V stream's products: 64 x 64 tiles (shorter
 // workgroups), ROLE 2 of k_gemm in FP64.
+// A product operand already split into BF16 pieces (presplit): `rows` rows
+// (M for op(A), N for op(B)), `piece` 16-byte chunks per piece.
+struct PsOperand {
+  const uint4* p;
+  int64_t rows, kc, piece;
+};
+// The kernel's view of the pre-split operands (unused ones NULL).
+struct PsOps {
+  const uint4* a;
+  const uint4* b;
+  int64_t rows_a, rows_b, piece_a, piece_b;
+};
+// psa / psb (may be NULL, BF16x3 and BF16x6 only): op(A) (M x K) / op(B)
+// (N x K, as rows) from presplit instead of A / B, which are then unused.
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc,
-                double* splitws, size_t splitws_elems, bool small_tiles = false);
+                double* splitws, size_t splitws_elems, bool small_tiles = false,
+                const PsOperand* psa = nullptr, const PsOperand* psb = nullptr);
+// Bytes of the pieces of an R x K operand in `prec` (0 unless BF16x3/BF16x6).
+size_t presplit_bytes(Prec prec, int64_t R, int64_t K);
+// Split op(X), R x K (element (r, k) = X[r + k ldx] when rcontig, else
+// X[k + r ldx]), into BF16 pieces at `out` (presplit_bytes, 16-byte aligned)
+// the way the GEMM loaders split FP64 operands, and describe them in *o.
+hipError_t presplit(hipStream_t st, Prec prec, int R, int K, const double* X, int64_t ldx,
+                    bool rcontig, void* out, PsOperand* o);
 // +1 / -1 around the products of a panel factorization: the FP64 products
 // in between launch their own kernel instantiation (same code), so traces
 // and counters tell them from the method's thin products.  Host-side, one

@@ -121,7 +121,7 @@ template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN, int ROLE>
 __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
     int M, int N, int K, int kper, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double* __restrict__ C, int64_t ldc,
-    int64_t zstride, double alpha, double beta) {
+    int64_t zstride, double alpha, double beta, PsOps ps) {
   constexpr int NT = 64 * WM * WN;                     // threads
   constexpr int BK = slab_k<P, BM>();
   constexpr int PM = BM / WM, PN = BN / WN;            // per-wave part
@@ -172,6 +172,16 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
   // slower).
   using LoadT = double;
   LoadT ra[LA], rb[LB];
+  // Operands given as BF16 pieces (ROLE bit 2: A, bit 3: B): 16-byte chunks
+  // of 8 consecutive k of one row, already in the LDS layout; CA (CB)
+  // chunks per thread and piece per slab.
+  constexpr bool PSA = (ROLE & 4) != 0, PSB = (ROLE & 8) != 0;
+  static_assert(!(PSA || PSB) || P == PREC_BF16X3 || P == PREC_BF16X6, "pre-split operands are BF16");
+  constexpr int NPC = P == PREC_BF16X6 ? 3 : 2;
+  constexpr int CA = PSA ? 4 * BM / NT : 1, CB = PSB ? 4 * BN / NT : 1;
+  static_assert(!PSA || CA * NT == 4 * BM, "pre-split A chunks");
+  static_assert(!PSB || CB * NT == 4 * BN, "pre-split B chunks");
+  uint4 pa[PSA ? NPC : 1][CA], pb[PSB ? NPC : 1][CB];
   // Slabs that lie wholly inside A (or B) take a path without per-element
   // guards: element r sits at a fixed offset from the thread's first one
   // (r * rsA, resp. r * rsB), and a slab moves by k0 * ksA (ksB).  The guards
@@ -189,7 +199,16 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
   const bool rowsA = m0 + BM <= M, colsB = n0 + BN <= N;
   auto load = [&](int k0) {
     const bool kin = k0 + BK <= kend;
-    if (rowsA && kin) {
+    if constexpr (PSA) {
+#pragma unroll
+      for (int u = 0; u < CA; ++u) {
+        const int c = tid + NT * u, kc = c / BM, r = c % BM;
+        const bool in = m0 + r < M;
+        const uint4* src = ps.a + ((int64_t)((k0 >> 3) + kc) * ps.rows_a + (m0 + r));
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) pa[q][u] = in ? src[q * ps.piece_a] : uint4{0, 0, 0, 0};
+      }
+    } else if (rowsA && kin) {
       const double* pa = A + offA + (int64_t)k0 * ksA;
 #pragma unroll
       for (int r = 0; r < LA; ++r) ra[r] = pa[r * rsA];
@@ -202,10 +221,19 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
         ra[r] = (gi < M && gk < kend) ? (TA ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : 0.0;
       }
     }
-    if (colsB && kin) {
-      const double* pb = B + offB + (int64_t)k0 * ksB;
+    if constexpr (PSB) {
 #pragma unroll
-      for (int r = 0; r < LB; ++r) rb[r] = pb[r * rsB];
+      for (int u = 0; u < CB; ++u) {
+        const int c = tid + NT * u, kc = c / BN, r = c % BN;
+        const bool in = n0 + r < N;
+        const uint4* src = ps.b + ((int64_t)((k0 >> 3) + kc) * ps.rows_b + (n0 + r));
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) pb[q][u] = in ? src[q * ps.piece_b] : uint4{0, 0, 0, 0};
+      }
+    } else if (colsB && kin) {
+      const double* pbb = B + offB + (int64_t)k0 * ksB;
+#pragma unroll
+      for (int r = 0; r < LB; ++r) rb[r] = pbb[r * rsB];
     } else {
 #pragma unroll
       for (int r = 0; r < LB; ++r) {
@@ -217,6 +245,19 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
     }
   };
   auto store = [&](int buf) {
+    if constexpr (PSA) {
+#pragma unroll
+      for (int u = 0; u < CA; ++u) {
+        const int c = tid + NT * u, kc = c / BM, r = c % BM;
+        *(uint4*)&sl.Ah[buf][kc][r][0] = pa[0][u];
+        if constexpr (P == PREC_BF16X6) {
+          *(uint4*)&sl.Am[buf][kc][r][0] = pa[1][u];
+          *(uint4*)&sl.Al[buf][kc][r][0] = pa[2][u];
+        } else {
+          *(uint4*)&sl.Al[buf][kc][r][0] = pa[1][u];
+        }
+      }
+    } else {
 #pragma unroll
     for (int r = 0; r < LA; ++r) {
       int i, k;
@@ -235,6 +276,20 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
         sl.Al[buf][k >> 3][i][k & 7] = (__bf16)(x - (float)h);
       }
     }
+    }
+    if constexpr (PSB) {
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int c = tid + NT * u, kc = c / BN, r = c % BN;
+        *(uint4*)&sl.Bh[buf][kc][r][0] = pb[0][u];
+        if constexpr (P == PREC_BF16X6) {
+          *(uint4*)&sl.Bm[buf][kc][r][0] = pb[1][u];
+          *(uint4*)&sl.Bl[buf][kc][r][0] = pb[2][u];
+        } else {
+          *(uint4*)&sl.Bl[buf][kc][r][0] = pb[1][u];
+        }
+      }
+    } else {
 #pragma unroll
     for (int r = 0; r < LB; ++r) {
       int k, j;
@@ -252,6 +307,7 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
         sl.Bh[buf][k >> 3][j][k & 7] = h;
         sl.Bl[buf][k >> 3][j][k & 7] = (__bf16)(x - (float)h);
       }
+    }
     }
   };
 
@@ -416,6 +472,49 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
   }
 }
 
+// op(X) (R x K: element (r, k) = X[r + k ldx] when rcontig, else X[k + r ldx])
+// split into NPC BF16 pieces exactly as k_gemm's loaders split it, in the
+// LDS slab layout: chunk (kc, r) holds k = 8 kc .. 8 kc + 7 of row r (zeros
+// from K on) at out[q * Kc * R + kc * R + r], piece q.
+template <int NPC>
+__global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, int64_t ldx,
+                           int rcontig, uint4* __restrict__ out) {
+  const int64_t total = (int64_t)Kc * R;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx % R), kc = (int)(idx / R);
+    unsigned short h[8], m[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 8 * kc + e;
+      const double v = k < K ? (rcontig ? X[r + (int64_t)k * ldx] : X[k + (int64_t)r * ldx]) : 0.0;
+      const float x = (float)v;
+      if constexpr (NPC == 3) {
+        const Bf3 p = split3(x);
+        h[e] = __builtin_bit_cast(unsigned short, p.h);
+        m[e] = __builtin_bit_cast(unsigned short, p.m);
+        l[e] = __builtin_bit_cast(unsigned short, p.l);
+      } else {
+        const __bf16 hb = (__bf16)x;
+        h[e] = __builtin_bit_cast(unsigned short, hb);
+        l[e] = __builtin_bit_cast(unsigned short, (__bf16)(x - (float)hb));
+        m[e] = 0;
+      }
+    }
+    auto pack = [](const unsigned short (&a)[8]) {
+      return uint4{a[0] | ((unsigned)a[1] << 16), a[2] | ((unsigned)a[3] << 16),
+                   a[4] | ((unsigned)a[5] << 16), a[6] | ((unsigned)a[7] << 16)};
+    };
+    out[idx] = pack(h);
+    if constexpr (NPC == 3) {
+      out[total + idx] = pack(m);
+      out[2 * total + idx] = pack(l);
+    } else {
+      out[total + idx] = pack(l);
+    }
+  }
+}
+
 // Small FP64 products (M, N <= kSmallMN, short K: the 128 x 128 blocks of
 // the panel factorizations).  One wave per 16 x 16 tile of C, operands read
 // straight from memory (L2) into the MFMA operand registers, eight K steps
@@ -502,19 +601,19 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ 
 template <int P, bool TA, bool TB, int BM, int BN, int WM, int WN, int ROLE>
 void launch(hipStream_t st, dim3 grid, int M, int N, int K, int kper, const double* A,
             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-            int64_t zstride, double alpha, double beta) {
+            int64_t zstride, double alpha, double beta, const PsOps& ps) {
   hipLaunchKernelGGL((k_gemm<P, TA, TB, BM, BN, WM, WN, ROLE>), grid, dim3(64 * WM * WN), 0, st, M, N, K,
-                     kper, A, lda, B, ldb, C, ldc, zstride, alpha, beta);
+                     kper, A, lda, B, ldb, C, ldc, zstride, alpha, beta, ps);
 }
 
 template <int P, int BM, int BN, int WM, int WN, int ROLE>
 void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, int kper,
               const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-              int64_t ldc, int64_t zs, double al, double be) {
-  if (!ta && !tb) launch<P, false, false, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (ta && !tb) launch<P, true, false, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (!ta && tb) launch<P, false, true, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else launch<P, true, true, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+              int64_t ldc, int64_t zs, double al, double be, const PsOps& ps) {
+  if (!ta && !tb) launch<P, false, false, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+  else if (ta && !tb) launch<P, true, false, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+  else if (!ta && tb) launch<P, false, true, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+  else launch<P, true, true, BM, BN, WM, WN, ROLE>(st, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
 }
 
 // Tile shapes: 0 = 64 x 64 on 2 x 2 waves; 1 = 128 x 128 on 2 x 2 waves, in
@@ -525,10 +624,24 @@ void launch_t(hipStream_t st, bool ta, bool tb, dim3 grid, int M, int N, int K, 
 template <int P, int ROLE = 0>
 void launch_p(hipStream_t st, int shape, bool ta, bool tb, dim3 grid, int M, int N, int K,
               int kper, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-              int64_t ldc, int64_t zs, double al, double be) {
-  if (shape == 1 && P == PREC_FP64) launch_t<P, 128, 128, 2, 4, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else if (shape == 1) launch_t<P, 128, 128, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
-  else launch_t<P, 64, 64, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be);
+              int64_t ldc, int64_t zs, double al, double be, const PsOps& ps = PsOps{}) {
+  if constexpr (P == PREC_FP64) {
+    if (shape == 1) launch_t<P, 128, 128, 2, 4, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+    else launch_t<P, 64, 64, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+  } else {
+    if (shape == 1) launch_t<P, 128, 128, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+    else launch_t<P, 64, 64, 2, 2, ROLE>(st, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+  }
+}
+
+// The BF16 products with pre-split operands: ROLE 4 (A), 8 (B) or 12 (both).
+template <int P>
+void launch_ps(hipStream_t st, int role, int shape, bool ta, bool tb, dim3 grid, int M, int N,
+               int K, int kper, const double* A, int64_t lda, const double* B, int64_t ldb,
+               double* C, int64_t ldc, int64_t zs, double al, double be, const PsOps& ps) {
+  if (role == 4) launch_p<P, 4>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+  else if (role == 8) launch_p<P, 8>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
+  else launch_p<P, 12>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, C, ldc, zs, al, be, ps);
 }
 
 int g_panel_scope = 0;  // > 0 while a panel factorization enqueues its products
@@ -547,8 +660,18 @@ constexpr int kSmallSplitMinK = SMALL_SPLIT_MIN_K;
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc, double* splitws,
-                size_t splitws_elems, bool small_tiles) {
+                size_t splitws_elems, bool small_tiles, const PsOperand* psa,
+                const PsOperand* psb) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  const int role_ps = (psa ? 4 : 0) | (psb ? 8 : 0);
+  if (role_ps) {
+    if (prec != PREC_BF16X3 && prec != PREC_BF16X6) return hipErrorInvalidValue;
+    const int64_t kc = (K + 31) / 32 * 4;
+    if ((psa && (psa->rows != M || psa->kc < kc)) || (psb && (psb->rows != N || psb->kc < kc)))
+      return hipErrorInvalidValue;
+  }
+  const PsOps ops{psa ? psa->p : nullptr, psb ? psb->p : nullptr, psa ? psa->rows : 0,
+                  psb ? psb->rows : 0, psa ? psa->piece : 0, psb ? psb->piece : 0};
   if (prec == PREC_FP64 && M <= kSmallMN && N <= kSmallMN && K <= kSmallK) {
     const dim3 grid((M + 15) / 16, (N + 15) / 16);
     const int slot = prof_mark(st, PC_GEMM_SMALL);
@@ -615,8 +738,12 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   const int slot = prof_mark(st, cls);
   if (prec == PREC_FP32)
     launch_p<PREC_FP32>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else if (prec == PREC_BF16X6 && role_ps)
+    launch_ps<PREC_BF16X6>(st, role_ps, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be, ops);
   else if (prec == PREC_BF16X6)
     launch_p<PREC_BF16X6>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
+  else if (prec == PREC_BF16X3 && role_ps)
+    launch_ps<PREC_BF16X3>(st, role_ps, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be, ops);
   else if (prec == PREC_BF16X3)
     launch_p<PREC_BF16X3>(st, shape, ta, tb, grid, M, N, K, kper, A, lda, B, ldb, Cout, ldo, zs, al, be);
   else if (uv)
@@ -636,6 +763,30 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
                      zs, C, ldc, alpha, beta);
   prof_done(st, slot2, PC_SPLITK, (double)splits * M * N,
             8.0 * (double)M * N * (splits + (beta != 0.0 ? 2 : 1)));
+  return hipGetLastError();
+}
+
+size_t presplit_bytes(Prec prec, int64_t R, int64_t K) {
+  if (prec != PREC_BF16X3 && prec != PREC_BF16X6) return 0;
+  const int64_t kc = (K + 31) / 32 * 4;  // 8-deep chunks, K padded to the 32-deep slab
+  return (size_t)(prec == PREC_BF16X6 ? 3 : 2) * kc * R * sizeof(uint4);
+}
+
+hipError_t presplit(hipStream_t st, Prec prec, int R, int K, const double* X, int64_t ldx,
+                    bool rcontig, void* out, PsOperand* o) {
+  if (prec != PREC_BF16X3 && prec != PREC_BF16X6) return hipErrorInvalidValue;
+  if (R < 0 || K < 0 || ((uintptr_t)out & 15)) return hipErrorInvalidValue;
+  const int kc = (K + 31) / 32 * 4;
+  *o = PsOperand{(const uint4*)out, R, kc, (int64_t)kc * R};
+  if (R == 0 || kc == 0) return hipSuccess;
+  const int64_t total = (int64_t)kc * R;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  if (prec == PREC_BF16X6)
+    hipLaunchKernelGGL(k_presplit<3>, dim3(blocks), dim3(256), 0, st, R, K, kc, X, ldx,
+                       rcontig ? 1 : 0, (uint4*)out);
+  else
+    hipLaunchKernelGGL(k_presplit<2>, dim3(blocks), dim3(256), 0, st, R, K, kc, X, ldx,
+                       rcontig ? 1 : 0, (uint4*)out);
   return hipGetLastError();
 }
 

@@ -133,6 +133,22 @@ Layout make_layout(int64_t m, int64_t n, int64_t b, int64_t p = 0) {
   return L;
 }
 
+// Split-precision factorizations also take two buffers for operands split
+// into BF16 pieces once per product (presplit), when the workspace holds
+// them: the thin operands of the sampling and update products, which every
+// workgroup of a product would otherwise read and split again.
+bool uses_bf16(int prec) {
+  const Prec ps = sampling_prec(prec), pu = update_prec(prec);
+  return ps == PREC_BF16X3 || ps == PREC_BF16X6 || pu == PREC_BF16X3 || pu == PREC_BF16X6;
+}
+size_t presplit_buf_bytes(int64_t m, int64_t n, int64_t bp) {
+  const int64_t r = std::max(m, n);
+  return al256(std::max(presplit_bytes(PREC_BF16X6, r, bp), presplit_bytes(PREC_BF16X6, bp, r)));
+}
+size_t factor_bytes(int64_t m, int64_t n, int64_t b, int64_t p, int prec) {
+  return make_layout(m, n, b, p).total + (uses_bf16(prec) ? 2 * presplit_buf_bytes(m, n, b + p) : 0);
+}
+
 
 // U and V accumulation runs on a second stream of the device (default
 // priority), ordered against the main stream by events: the panels and
@@ -362,7 +378,7 @@ int randutv_workspace_size_p(int64_t m, int64_t n, int64_t b, int64_t p, int q, 
   if (prec < 0 || prec > kPrecMax) return -6;
   if (!valid_flags(flags)) return -7;
   if (!bytes) return -8;
-  *bytes = make_layout(m, n, b, p).total;
+  *bytes = factor_bytes(m, n, b, p, prec);
   return 0;
 }
 
@@ -380,7 +396,7 @@ int randutv_workspace_size_lower(int64_t m, int64_t n, int64_t b, int q, int pre
   if (prec < 0 || prec > kPrecMax) return -5;
   if (flags & ~(unsigned)(RANDUTV_FORM_U | RANDUTV_FORM_V)) return -6;
   if (!bytes) return -7;
-  *bytes = make_layout(n, m, b).total + al256((size_t)m * n * sizeof(double));
+  *bytes = factor_bytes(n, m, b, 0, prec) + al256((size_t)m * n * sizeof(double));
   return 0;
 }
 
@@ -392,7 +408,7 @@ int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q, int prec, uns
   if (prec < 0 || prec > kPrecMax) return -5;
   if (!valid_flags(flags)) return -6;
   if (!bytes) return -7;
-  *bytes = make_layout(m, n, b).total;
+  *bytes = factor_bytes(m, n, b, 0, prec);
   return 0;
 }
 
@@ -436,7 +452,7 @@ int randutv_factor_lower(int64_t m, int64_t n, int64_t b, int q, double* T, int6
   hipStream_t st = (hipStream_t)stream;
   // The inner factorization's workspace comes first (its status words at
   // offset 0), then A^T (n x m).
-  const size_t fb = make_layout(n, m, b).total;
+  const size_t fb = factor_bytes(n, m, b, 0, prec);
   double* Tt = (double*)((char*)work + fb);
   HIPCHK(transpose(st, (int)m, (int)n, T, ldt, Tt, n));
   // A^T = U' T' V'^T, so A = V' T'^T U'^T: U of A^T goes to V, V of A^T to U.
@@ -499,6 +515,8 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   if (!work || ((uintptr_t)work & 255)) return -12;
   const Layout L = make_layout(m, n, b, p);
   if (work_bytes < L.total) return RANDUTV_E_WORKSPACE;
+  const size_t psb = presplit_buf_bytes(m, n, b + p);
+  const bool use_ps = uses_bf16(prec) && work_bytes >= L.total + 2 * psb;
 
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(g_mu);
@@ -529,6 +547,25 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   const int Bp = (int)(b + p);    // samples per randomized step
   const int MN = std::max(M, N);  // leading dimension of the U / V stream products
   int* intsY = p > 0 ? (int*)(base + L.intsY) : nullptr;
+  // Buffers of the pre-split operands (use_ps), and the product through them:
+  // op(A) from A (rows M, rcontig when A is not transposed) if sa, op(B)
+  // from B (rows N, rcontig when B is transposed) if sb; plain gemm when
+  // the product's arithmetic is not BF16 or the buffers are absent.
+  void* psA = use_ps ? (void*)(base + L.total) : nullptr;
+  void* psB = use_ps ? (void*)(base + L.total + psb) : nullptr;
+  auto gemm_ps = [&](Prec pr, bool ta, bool tb, int Mq, int Nq, int Kq, double al,
+                     const double* Aq, int64_t lda, const double* Bq, int64_t ldb, double be,
+                     double* Cq, int64_t ldc, double* sp, size_t spe, bool sa,
+                     bool sb) -> hipError_t {
+    if (!use_ps || !(pr == PREC_BF16X3 || pr == PREC_BF16X6) || Mq <= 0 || Nq <= 0 || Kq <= 0)
+      return gemm(st, pr, ta, tb, Mq, Nq, Kq, al, Aq, lda, Bq, ldb, be, Cq, ldc, sp, spe);
+    PsOperand oa{}, ob{};
+    hipError_t e = hipSuccess;
+    if (sa && (e = presplit(st, pr, Mq, Kq, Aq, lda, !ta, psA, &oa)) != hipSuccess) return e;
+    if (sb && (e = presplit(st, pr, Nq, Kq, Bq, ldb, tb, psB, &ob)) != hipSuccess) return e;
+    return gemm(st, pr, ta, tb, Mq, Nq, Kq, al, Aq, lda, Bq, ldb, be, Cq, ldc, sp, spe, false,
+                sa ? &oa : nullptr, sb ? &ob : nullptr);
+  };
 
   double *VhS[kSlots], *UhS[kSlots], *TwVS[kSlots], *TwUS[kSlots];
   for (int k = 0; k < kSlots; ++k)
@@ -608,10 +645,10 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     if (r0 + B < M && r0 + B < N) {
       const double* Gi = G + (int64_t)i * Bp * ldg;
       // Sampling matrix Y = (X^T X)^q X^T G_i (b + p columns).
-      HIPCHK(gemm(st, ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se));
+      HIPCHK(gemm_ps(ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se, false, true));
       for (int it = 0; it < q; ++it) {
-        HIPCHK(gemm(st, ps, false, false, Mi, Bp, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se));
-        HIPCHK(gemm(st, ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se));
+        HIPCHK(gemm_ps(ps, false, false, Mi, Bp, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se, false, true));
+        HIPCHK(gemm_ps(ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se, false, true));
       }
       if (p > 0) HIPCHK(oversample_basis(st, Ni, B, Bp, Y, N, L, base, intsY + (size_t)i * kIntsY,
                                          hw, pw, split, se, &blk->svd_fail));
@@ -620,9 +657,9 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       HIPCHK(panel_qr_hr(st, Ni, B, Y, N, Vh, N, RV, B, tauV, TwV, B, hw, pw, split, se));
       // Right transform of T's trailing columns, all m rows.
       double* TJ = T + (int64_t)r0 * ldt;
-      HIPCHK(gemm(st, pu, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se));
+      HIPCHK(gemm_ps(pu, false, false, M, B, Ni, 1.0, TJ, ldt, Vh, N, 0.0, W, M, split, se, false, true));
       HIPCHK(gemm(st, PREC_FP64, false, false, M, B, B, 1.0, W, M, TwV, B, 0.0, W2, M, nullptr, 0));
-      HIPCHK(gemm(st, pu, false, true, M, Ni, B, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0));
+      HIPCHK(gemm_ps(pu, false, true, M, Ni, B, -1.0, W2, M, Vh, N, 1.0, TJ, ldt, nullptr, 0, true, true));
       if (formV) {  // V(:, J) = V(:, J) Vq, on the U / V stream
         double* VJ = V + (int64_t)r0 * ldv;
         HIPCHK(to_side(kVR + sl));
@@ -640,9 +677,9 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       // Left transform of the trailing rows right of the block.
       const int Nr = Ni - B;
       double* XJ3 = X + (int64_t)B * ldt;
-      HIPCHK(gemm(st, pu, true, false, B, Nr, Mi, 1.0, Uh, ldUh, XJ3, ldt, 0.0, C, B, split, se));
+      HIPCHK(gemm_ps(pu, true, false, B, Nr, Mi, 1.0, Uh, ldUh, XJ3, ldt, 0.0, C, B, split, se, true, false));
       HIPCHK(gemm(st, PREC_FP64, true, false, B, Nr, B, 1.0, TwU, B, C, B, 0.0, C2, B, nullptr, 0));
-      HIPCHK(gemm(st, pu, false, false, Mi, Nr, B, -1.0, Uh, ldUh, C2, B, 1.0, XJ3, ldt, nullptr, 0));
+      HIPCHK(gemm_ps(pu, false, false, Mi, Nr, B, -1.0, Uh, ldUh, C2, B, 1.0, XJ3, ldt, nullptr, 0, true, true));
       // U's trailing columns times the left transform (forward accumulation)
       if (formU && !econU) {  // on the U / V stream
         double* UI = U + (int64_t)r0 * ldu;
