@@ -134,15 +134,43 @@ def dominant_class(prof, arith=None):
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_symbol(cls):
+# Sampling and update arithmetic of each split path.
+PATH_ARITH = {"bf16x3": ("bf16x3", "bf16x3"), "bf16x3_fp32": ("bf16x3", "fp32"),
+              "bf16x3_bf16x6": ("bf16x3", "bf16x6"), "fp32": ("fp32", "fp32"),
+              "fp64": ("fp64", "fp64")}
+
+
+def bf16_roles(cls, path):
+    """ROLE values of the k_gemm instantiations a BF16 class runs in the
+    factorization of `path`, whose thin operands come pre-split: bit 2 for
+    op(A), bit 3 for op(B).  Sampling Y = X^T G, Z = X Y (B split: 8); right
+    update W = T Vh (8) and T -= W2 Vh^T (12); left update C = Uh^T T (4)
+    and T -= Uh C2 (12)."""
+    op, arith = cls.split("_")[1:3]
+    ps, pu = PATH_ARITH.get(path, (None, None))
+    roles = set()
+    if arith == ps:
+        roles |= {"tn": {8}, "nn": {8}}.get(op, set())
+    if arith == pu:
+        roles |= {"nn": {8, 12}, "nt": {12}, "tn": {4}}.get(op, set())
+    return sorted(roles) or [0]
+
+
+def kernel_symbol(cls, path=None):
     """k_gemm instantiation of a class name gemm_<op(A)op(B)>_<arith>_t<tile>,
-    with a _uv suffix for the U / V stream's products (ROLE 2; else 0)."""
+    with a _uv suffix for the U / V stream's products (ROLE 2; else 0).  A
+    BF16 class of a split path's factorization (path given) names each
+    instantiation it runs, joined by " | "."""
     parts = cls.split("_")
     _, op, arith, tile = parts[:4]
-    role = 2 if parts[4:] == ["uv"] else 0
+    roles = [2 if parts[4:] == ["uv"] else 0]
+    if path and arith.startswith("bf16"):
+        roles = bf16_roles(cls, path)
     waves = "2, 4" if (arith, tile) == ("fp64", "t128") else "2, 2"  # FP64 128 x 128: 2 x 4 waves
-    return (f"k_gemm<PREC_{arith.upper()}, {'true' if op[0] == 't' else 'false'}, "
-            f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, {waves}, {role}>")
+    return " | ".join(
+        f"k_gemm<PREC_{arith.upper()}, {'true' if op[0] == 't' else 'false'}, "
+        f"{'true' if op[1] == 't' else 'false'}, {tile[1:]}, {tile[1:]}, {waves}, {role}>"
+        for role in roles)
 
 
 def roofline_of(dom, prof_dom, workload):
@@ -728,7 +756,7 @@ def main():
         ms_b, fl_b, by_b, nl_b = paths[bpath]["dom"][2][bcls]
         t = ms_b * 1e-3
         nprod = BF16_PRODUCTS[bcls.split("_")[2]]
-        bf16_split = {"path": bpath, "class": bcls, "kernel": kernel_symbol(bcls),
+        bf16_split = {"path": bpath, "class": bcls, "kernel": kernel_symbol(bcls, bpath),
                       "avg_launch_us": ms_b / nl_b * 1e3,
                       "product_tflops": fl_b / t / 1e12,
                       "bf16_mfma_tflops": nprod * fl_b / t / 1e12,

@@ -51,6 +51,15 @@ def test_roofline_record_arithmetic():
     assert r["kernel"] == "k_gemm<PREC_FP64, false, true, 128, 128, 2, 4, 0>"
     assert bench.kernel_symbol("gemm_nt_fp64_t64_uv") == \
         "k_gemm<PREC_FP64, false, true, 64, 64, 2, 2, 2>"
+    # BF16 classes of a split path name the pre-split instantiations they run.
+    assert bench.kernel_symbol("gemm_nn_bf16x6_t128", "bf16x3_bf16x6") == (
+        "k_gemm<PREC_BF16X6, false, false, 128, 128, 2, 2, 8> | "
+        "k_gemm<PREC_BF16X6, false, false, 128, 128, 2, 2, 12>")
+    assert bench.kernel_symbol("gemm_tn_bf16x3_t128", "bf16x3_bf16x6") == \
+        "k_gemm<PREC_BF16X3, true, false, 128, 128, 2, 2, 8>"
+    assert bench.kernel_symbol("gemm_tn_bf16x3_t128", "bf16x3") == (
+        "k_gemm<PREC_BF16X3, true, false, 128, 128, 2, 2, 4> | "
+        "k_gemm<PREC_BF16X3, true, false, 128, 128, 2, 2, 8>")
     prof["gemm_nt_fp64_t128@alone"] = (5.0, 5e11, 2e9, 100)
     r = bench.roofline_of("gemm_nt_fp64_t128", prof, WORKLOAD)
     assert r["achieved_alone"] == pytest.approx(100.0)
