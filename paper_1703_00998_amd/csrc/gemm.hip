@@ -259,23 +259,23 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
       }
     } else {
 #pragma unroll
-    for (int r = 0; r < LA; ++r) {
-      int i, k;
-      a_idx(r, i, k);
-      if constexpr (P == PREC_FP64) sl.A[buf][k][i] = ra[r];
-      else if constexpr (P == PREC_FP32) sl.A[buf][k][i] = (float)ra[r];
-      else if constexpr (P == PREC_BF16X6) {
-        const Bf3 x = split3((float)ra[r]);
-        sl.Ah[buf][k >> 3][i][k & 7] = x.h;
-        sl.Am[buf][k >> 3][i][k & 7] = x.m;
-        sl.Al[buf][k >> 3][i][k & 7] = x.l;
-      } else {
-        const float x = (float)ra[r];
-        const __bf16 h = (__bf16)x;
-        sl.Ah[buf][k >> 3][i][k & 7] = h;
-        sl.Al[buf][k >> 3][i][k & 7] = (__bf16)(x - (float)h);
+      for (int r = 0; r < LA; ++r) {
+        int i, k;
+        a_idx(r, i, k);
+        if constexpr (P == PREC_FP64) sl.A[buf][k][i] = ra[r];
+        else if constexpr (P == PREC_FP32) sl.A[buf][k][i] = (float)ra[r];
+        else if constexpr (P == PREC_BF16X6) {
+          const Bf3 x = split3((float)ra[r]);
+          sl.Ah[buf][k >> 3][i][k & 7] = x.h;
+          sl.Am[buf][k >> 3][i][k & 7] = x.m;
+          sl.Al[buf][k >> 3][i][k & 7] = x.l;
+        } else {
+          const float x = (float)ra[r];
+          const __bf16 h = (__bf16)x;
+          sl.Ah[buf][k >> 3][i][k & 7] = h;
+          sl.Al[buf][k >> 3][i][k & 7] = (__bf16)(x - (float)h);
+        }
       }
-    }
     }
     if constexpr (PSB) {
 #pragma unroll
@@ -291,23 +291,23 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
       }
     } else {
 #pragma unroll
-    for (int r = 0; r < LB; ++r) {
-      int k, j;
-      b_idx(r, k, j);
-      if constexpr (P == PREC_FP64) sl.B[buf][k][j] = rb[r];
-      else if constexpr (P == PREC_FP32) sl.B[buf][k][j] = (float)rb[r];
-      else if constexpr (P == PREC_BF16X6) {
-        const Bf3 x = split3((float)rb[r]);
-        sl.Bh[buf][k >> 3][j][k & 7] = x.h;
-        sl.Bm[buf][k >> 3][j][k & 7] = x.m;
-        sl.Bl[buf][k >> 3][j][k & 7] = x.l;
-      } else {
-        const float x = (float)rb[r];
-        const __bf16 h = (__bf16)x;
-        sl.Bh[buf][k >> 3][j][k & 7] = h;
-        sl.Bl[buf][k >> 3][j][k & 7] = (__bf16)(x - (float)h);
+      for (int r = 0; r < LB; ++r) {
+        int k, j;
+        b_idx(r, k, j);
+        if constexpr (P == PREC_FP64) sl.B[buf][k][j] = rb[r];
+        else if constexpr (P == PREC_FP32) sl.B[buf][k][j] = (float)rb[r];
+        else if constexpr (P == PREC_BF16X6) {
+          const Bf3 x = split3((float)rb[r]);
+          sl.Bh[buf][k >> 3][j][k & 7] = x.h;
+          sl.Bm[buf][k >> 3][j][k & 7] = x.m;
+          sl.Bl[buf][k >> 3][j][k & 7] = x.l;
+        } else {
+          const float x = (float)rb[r];
+          const __bf16 h = (__bf16)x;
+          sl.Bh[buf][k >> 3][j][k & 7] = h;
+          sl.Bl[buf][k >> 3][j][k & 7] = (__bf16)(x - (float)h);
+        }
       }
-    }
     }
   };
 
@@ -476,13 +476,30 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
 // split into NPC BF16 pieces exactly as k_gemm's loaders split it, in the
 // LDS slab layout: chunk (kc, r) holds k = 8 kc .. 8 kc + 7 of row r (zeros
 // from K on) at out[q * Kc * R + kc * R + r], piece q.
+// Thread w takes chunk (kc, r): with rcontig, r = w mod R (consecutive lanes
+// read consecutive rows at each k); otherwise lanes go in 8 x 8 tiles, lane
+// l on kc = 8 kt + l mod 8, r = 8 rt + l / 8, so that eight lanes read 512
+// contiguous bytes of one column and eight lanes write 128 contiguous bytes.
 template <int NPC>
 __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, int64_t ldx,
                            int rcontig, uint4* __restrict__ out) {
   const int64_t total = (int64_t)Kc * R;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(idx % R), kc = (int)(idx / R);
+  const int rt8 = (R + 7) / 8;
+  const int64_t span = rcontig ? total : (int64_t)((Kc + 7) / 8) * rt8 * 64;
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < span;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    int r, kc;
+    if (rcontig) {
+      r = (int)(w % R);
+      kc = (int)(w / R);
+    } else {
+      const int64_t tile = w >> 6;
+      const int l = (int)(w & 63);
+      kc = (int)(tile / rt8) * 8 + (l & 7);
+      r = (int)(tile % rt8) * 8 + (l >> 3);
+      if (kc >= Kc || r >= R) continue;
+    }
+    const int64_t idx = (int64_t)kc * R + r;
     unsigned short h[8], m[8], l[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -779,7 +796,7 @@ hipError_t presplit(hipStream_t st, Prec prec, int R, int K, const double* X, in
   const int kc = (K + 31) / 32 * 4;
   *o = PsOperand{(const uint4*)out, R, kc, (int64_t)kc * R};
   if (R == 0 || kc == 0) return hipSuccess;
-  const int64_t total = (int64_t)kc * R;
+  const int64_t total = rcontig ? (int64_t)kc * R : (int64_t)((kc + 7) / 8) * ((R + 7) / 8) * 64;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   if (prec == PREC_BF16X6)
     hipLaunchKernelGGL(k_presplit<3>, dim3(blocks), dim3(256), 0, st, R, K, kc, X, ldx,
