@@ -83,7 +83,11 @@ int64_t randutv_random_steps(int64_t m, int64_t n, int64_t b);
 int64_t randutv_g_cols(int64_t m, int64_t n, int64_t b);
 
 /* Bytes of device workspace randutv_factor needs for these arguments
- * (written to *bytes).  Returns a status as above. */
+ * (written to *bytes).  Returns a status as above.  For the arithmetics
+ * with BF16 products this includes two buffers in which each product's
+ * thin operand is split into BF16 pieces once (Section 5.4's thin
+ * products); a call given only the FP64 workspace size computes the same
+ * factorization, splitting the operands inside its product kernels. */
 int randutv_workspace_size(int64_t m, int64_t n, int64_t b, int q,
                            int prec, unsigned flags, size_t* bytes);
 
