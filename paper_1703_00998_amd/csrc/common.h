@@ -81,20 +81,34 @@ struct PsOps {
   const uint4* b;
   int64_t rows_a, rows_b, piece_a, piece_b;
 };
+// Where a product's result is: p with leading dimension ld, as `splits`
+// FP64 partials zs apart (to be summed in order) or one matrix (splits 1).
+struct SplitKeep {
+  const double* p;
+  int64_t ld;
+  int splits;
+  int64_t zs;
+};
 // psa / psb (may be NULL, BF16x3 and BF16x6 only): op(A) (M x K) / op(B)
 // (N x K, as rows) from presplit instead of A / B, which are then unused.
+// keep (may be NULL): with alpha 1 and beta 0 a split-K product skips its
+// reduction and leaves the partials in splitws for the consumer (presplit
+// with S > 1); *keep says where the result is (C itself when not split).
 hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K,
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc,
                 double* splitws, size_t splitws_elems, bool small_tiles = false,
-                const PsOperand* psa = nullptr, const PsOperand* psb = nullptr);
+                const PsOperand* psa = nullptr, const PsOperand* psb = nullptr,
+                SplitKeep* keep = nullptr);
 // Bytes of the pieces of an R x K operand in `prec` (0 unless BF16x3/BF16x6).
 size_t presplit_bytes(Prec prec, int64_t R, int64_t K);
 // Split op(X), R x K (element (r, k) = X[r + k ldx] when rcontig, else
 // X[k + r ldx]), into BF16 pieces at `out` (presplit_bytes, 16-byte aligned)
 // the way the GEMM loaders split FP64 operands, and describe them in *o.
+// With S > 1, X holds S split-K partials zs doubles apart (SplitKeep) and
+// op(X) is their sum.
 hipError_t presplit(hipStream_t st, Prec prec, int R, int K, const double* X, int64_t ldx,
-                    bool rcontig, void* out, PsOperand* o);
+                    bool rcontig, void* out, PsOperand* o, int S = 1, int64_t zs = 0);
 // +1 / -1 around the products of a panel factorization: the FP64 products
 // in between launch their own kernel instantiation (same code), so traces
 // and counters tell them from the method's thin products.  Host-side, one

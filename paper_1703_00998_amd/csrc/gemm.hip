@@ -91,6 +91,18 @@ struct Slabs<PREC_BF16X6, BM, BN, NB> {
   alignas(16) __bf16 Bl[NB][4][BN][8];
 };
 
+// fl32(x): x rounded to FP32 (to nearest), held as a float.  The empty asm
+// keeps the compiler from merging this rounding with a following rounding
+// to BF16 into one direct FP64 -> BF16 rounding (through a round-to-odd
+// FP32, a handful of extra instructions per value), which it does in some
+// contexts and not in others: with it every loader and k_presplit take the
+// BF16 pieces of the same FP32 value, as written.
+__device__ inline float fl32(double x) {
+  float r = (float)x;
+  asm volatile("" : "+v"(r));
+  return r;
+}
+
 // x ~ h + m + l in bf16, from x32 = fl32(x): each piece is the bf16 rounding
 // of what the earlier ones leave (the remainders are exact in FP32), so the
 // three carry about 24 significant bits.
@@ -265,12 +277,12 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
         if constexpr (P == PREC_FP64) sl.A[buf][k][i] = ra[r];
         else if constexpr (P == PREC_FP32) sl.A[buf][k][i] = (float)ra[r];
         else if constexpr (P == PREC_BF16X6) {
-          const Bf3 x = split3((float)ra[r]);
+          const Bf3 x = split3(fl32(ra[r]));
           sl.Ah[buf][k >> 3][i][k & 7] = x.h;
           sl.Am[buf][k >> 3][i][k & 7] = x.m;
           sl.Al[buf][k >> 3][i][k & 7] = x.l;
         } else {
-          const float x = (float)ra[r];
+          const float x = fl32(ra[r]);
           const __bf16 h = (__bf16)x;
           sl.Ah[buf][k >> 3][i][k & 7] = h;
           sl.Al[buf][k >> 3][i][k & 7] = (__bf16)(x - (float)h);
@@ -297,12 +309,12 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
         if constexpr (P == PREC_FP64) sl.B[buf][k][j] = rb[r];
         else if constexpr (P == PREC_FP32) sl.B[buf][k][j] = (float)rb[r];
         else if constexpr (P == PREC_BF16X6) {
-          const Bf3 x = split3((float)rb[r]);
+          const Bf3 x = split3(fl32(rb[r]));
           sl.Bh[buf][k >> 3][j][k & 7] = x.h;
           sl.Bm[buf][k >> 3][j][k & 7] = x.m;
           sl.Bl[buf][k >> 3][j][k & 7] = x.l;
         } else {
-          const float x = (float)rb[r];
+          const float x = fl32(rb[r]);
           const __bf16 h = (__bf16)x;
           sl.Bh[buf][k >> 3][j][k & 7] = h;
           sl.Bl[buf][k >> 3][j][k & 7] = (__bf16)(x - (float)h);
@@ -476,13 +488,16 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
 // split into NPC BF16 pieces exactly as k_gemm's loaders split it, in the
 // LDS slab layout: chunk (kc, r) holds k = 8 kc .. 8 kc + 7 of row r (zeros
 // from K on) at out[q * Kc * R + kc * R + r], piece q.
+// With S > 1, X holds S split-K partials zs apart and op(X) is their sum,
+// taken as k_splitk_reduce takes it (alpha 1, beta 0), so the pieces are
+// those of the reduced matrix and the reduction launch is saved.
 // Thread w takes chunk (kc, r): with rcontig, r = w mod R (consecutive lanes
 // read consecutive rows at each k); otherwise lanes go in 8 x 8 tiles, lane
 // l on kc = 8 kt + l mod 8, r = 8 rt + l / 8, so that eight lanes read 512
 // contiguous bytes of one column and eight lanes write 128 contiguous bytes.
 template <int NPC>
 __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, int64_t ldx,
-                           int rcontig, uint4* __restrict__ out) {
+                           int rcontig, int S, int64_t zs, uint4* __restrict__ out) {
   const int64_t total = (int64_t)Kc * R;
   const int rt8 = (R + 7) / 8;
   const int64_t span = rcontig ? total : (int64_t)((Kc + 7) / 8) * rt8 * 64;
@@ -504,8 +519,16 @@ __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, i
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int k = 8 * kc + e;
-      const double v = k < K ? (rcontig ? X[r + (int64_t)k * ldx] : X[k + (int64_t)r * ldx]) : 0.0;
-      const float x = (float)v;
+      double v = 0.0;
+      if (k < K) {
+        const int64_t o = rcontig ? r + (int64_t)k * ldx : k + (int64_t)r * ldx;
+        if (S == 1) {
+          v = X[o];
+        } else {  // split-K partials, summed in k_splitk_reduce's order
+          for (int z = 0; z < S; ++z) v += X[z * zs + o];
+        }
+      }
+      const float x = fl32(v);
       if constexpr (NPC == 3) {
         const Bf3 p = split3(x);
         h[e] = __builtin_bit_cast(unsigned short, p.h);
@@ -678,7 +701,7 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
                 double alpha, const double* A, int64_t lda, const double* B,
                 int64_t ldb, double beta, double* C, int64_t ldc, double* splitws,
                 size_t splitws_elems, bool small_tiles, const PsOperand* psa,
-                const PsOperand* psb) {
+                const PsOperand* psb, SplitKeep* keep) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int role_ps = (psa ? 4 : 0) | (psb ? 8 : 0);
   if (role_ps) {
@@ -772,7 +795,12 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   prof_done(st, slot, cls, 2.0 * M * N * (double)K,
             8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)));
   hipError_t e = hipGetLastError();
+  if (keep) *keep = SplitKeep{C, ldc, 1, 0};
   if (e != hipSuccess || splits == 1) return e;
+  if (keep && alpha == 1.0 && beta == 0.0) {  // the consumer sums the partials
+    *keep = SplitKeep{splitws, M, splits, zs};
+    return e;
+  }
   const int64_t total = (int64_t)M * N;
   int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   const int slot2 = prof_mark(st, PC_SPLITK);
@@ -790,9 +818,9 @@ size_t presplit_bytes(Prec prec, int64_t R, int64_t K) {
 }
 
 hipError_t presplit(hipStream_t st, Prec prec, int R, int K, const double* X, int64_t ldx,
-                    bool rcontig, void* out, PsOperand* o) {
+                    bool rcontig, void* out, PsOperand* o, int S, int64_t zs) {
   if (prec != PREC_BF16X3 && prec != PREC_BF16X6) return hipErrorInvalidValue;
-  if (R < 0 || K < 0 || ((uintptr_t)out & 15)) return hipErrorInvalidValue;
+  if (R < 0 || K < 0 || S < 1 || ((uintptr_t)out & 15)) return hipErrorInvalidValue;
   const int kc = (K + 31) / 32 * 4;
   *o = PsOperand{(const uint4*)out, R, kc, (int64_t)kc * R};
   if (R == 0 || kc == 0) return hipSuccess;
@@ -800,10 +828,10 @@ hipError_t presplit(hipStream_t st, Prec prec, int R, int K, const double* X, in
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
   if (prec == PREC_BF16X6)
     hipLaunchKernelGGL(k_presplit<3>, dim3(blocks), dim3(256), 0, st, R, K, kc, X, ldx,
-                       rcontig ? 1 : 0, (uint4*)out);
+                       rcontig ? 1 : 0, S, zs, (uint4*)out);
   else
     hipLaunchKernelGGL(k_presplit<2>, dim3(blocks), dim3(256), 0, st, R, K, kc, X, ldx,
-                       rcontig ? 1 : 0, (uint4*)out);
+                       rcontig ? 1 : 0, S, zs, (uint4*)out);
   return hipGetLastError();
 }
 

@@ -553,18 +553,25 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   // the product's arithmetic is not BF16 or the buffers are absent.
   void* psA = use_ps ? (void*)(base + L.total) : nullptr;
   void* psB = use_ps ? (void*)(base + L.total + psb) : nullptr;
+  // With pre-split operands, inB (a SplitKeep, B not transposed) takes op(B)
+  // from the previous product's unreduced partials, and out keeps this
+  // product's partials for the next one (alpha 1, beta 0).
   auto gemm_ps = [&](Prec pr, bool ta, bool tb, int Mq, int Nq, int Kq, double al,
                      const double* Aq, int64_t lda, const double* Bq, int64_t ldb, double be,
-                     double* Cq, int64_t ldc, double* sp, size_t spe, bool sa,
-                     bool sb) -> hipError_t {
+                     double* Cq, int64_t ldc, double* sp, size_t spe, bool sa, bool sb,
+                     const SplitKeep* inB = nullptr, SplitKeep* out = nullptr) -> hipError_t {
     if (!use_ps || !(pr == PREC_BF16X3 || pr == PREC_BF16X6) || Mq <= 0 || Nq <= 0 || Kq <= 0)
       return gemm(st, pr, ta, tb, Mq, Nq, Kq, al, Aq, lda, Bq, ldb, be, Cq, ldc, sp, spe);
     PsOperand oa{}, ob{};
     hipError_t e = hipSuccess;
     if (sa && (e = presplit(st, pr, Mq, Kq, Aq, lda, !ta, psA, &oa)) != hipSuccess) return e;
-    if (sb && (e = presplit(st, pr, Nq, Kq, Bq, ldb, tb, psB, &ob)) != hipSuccess) return e;
+    if (sb) {
+      e = inB ? presplit(st, pr, Nq, Kq, inB->p, inB->ld, false, psB, &ob, inB->splits, inB->zs)
+              : presplit(st, pr, Nq, Kq, Bq, ldb, tb, psB, &ob);
+      if (e != hipSuccess) return e;
+    }
     return gemm(st, pr, ta, tb, Mq, Nq, Kq, al, Aq, lda, Bq, ldb, be, Cq, ldc, sp, spe, false,
-                sa ? &oa : nullptr, sb ? &ob : nullptr);
+                sa ? &oa : nullptr, sb ? &ob : nullptr, out);
   };
 
   double *VhS[kSlots], *UhS[kSlots], *TwVS[kSlots], *TwUS[kSlots];
@@ -645,10 +652,18 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
     if (r0 + B < M && r0 + B < N) {
       const double* Gi = G + (int64_t)i * Bp * ldg;
       // Sampling matrix Y = (X^T X)^q X^T G_i (b + p columns).
-      HIPCHK(gemm_ps(ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se, false, true));
+      // With pre-split operands the intermediate samples stay unreduced: each
+      // next product's pre-split sums their partials (fuse); the last Y is
+      // reduced into Y for the panel.
+      const bool fuse = use_ps && (ps == PREC_BF16X3 || ps == PREC_BF16X6);
+      SplitKeep kY{}, kZ{};
+      HIPCHK(gemm_ps(ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Gi, ldg, 0.0, Y, N, split, se,
+                     false, true, nullptr, fuse && q > 0 ? &kY : nullptr));
       for (int it = 0; it < q; ++it) {
-        HIPCHK(gemm_ps(ps, false, false, Mi, Bp, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se, false, true));
-        HIPCHK(gemm_ps(ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se, false, true));
+        HIPCHK(gemm_ps(ps, false, false, Mi, Bp, Ni, 1.0, X, ldt, Y, N, 0.0, Z, M, split, se,
+                       false, true, fuse ? &kY : nullptr, fuse ? &kZ : nullptr));
+        HIPCHK(gemm_ps(ps, true, false, Ni, Bp, Mi, 1.0, X, ldt, Z, M, 0.0, Y, N, split, se,
+                       false, true, fuse ? &kZ : nullptr, fuse && it + 1 < q ? &kY : nullptr));
       }
       if (p > 0) HIPCHK(oversample_basis(st, Ni, B, Bp, Y, N, L, base, intsY + (size_t)i * kIntsY,
                                          hw, pw, split, se, &blk->svd_fail));
