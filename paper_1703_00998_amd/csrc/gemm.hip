@@ -556,32 +556,38 @@ __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, i
 }
 
 // Small FP64 products (M, N <= kSmallMN, short K: the 128 x 128 blocks of
-// the panel factorizations).  One wave per 16 x 16 tile of C, operands read
-// straight from memory (L2) into the MFMA operand registers, eight K steps
-// of loads in flight at a time and two accumulators.  Spreads a 128 x 128
-// product over 64 CUs, where the LDS-tiled kernel puts it on four.
+// the panel factorizations).  Four waves per 16 x 16 tile of C, wave w
+// taking the w-th quarter of K (a multiple of 4 deep), with its operands
+// read straight from memory (L2) into the MFMA operand registers, eight K
+// steps of loads in flight at a time and two accumulators; the four partial
+// tiles are summed in wave order through LDS.  A 128-deep product then waits
+// for one round trip of loads instead of four.  Spreads a 128 x 128 product
+// over 64 CUs, where the LDS-tiled kernel puts it on four.
 // Same transposed MFMA orientation as k_gemm: register r of lane l holds
 // C(m0 + (l & 15), n0 + (l >> 4) + 4 r).
+constexpr int kSmallWaves = 4;
 template <bool TA, bool TB>
-__global__ __launch_bounds__(64) void k_gemm_small(int M, int N, int K, const double* __restrict__ A,
-                                                    int64_t lda, const double* __restrict__ B,
-                                                    int64_t ldb, double* __restrict__ C,
-                                                    int64_t ldc, double alpha, double beta) {
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(64 * kSmallWaves) void k_gemm_small(
+    int M, int N, int K, const double* __restrict__ A, int64_t lda, const double* __restrict__ B,
+    int64_t ldb, double* __restrict__ C, int64_t ldc, double alpha, double beta) {
+  __shared__ v4d part[kSmallWaves - 1][64];  // the partial tiles of waves 1, 2, 3
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 16;
   const int li = lane & 15, lk = lane >> 4;
   const int ia = m0 + li, jb = n0 + li;  // row of op(A), column of op(B) this lane reads
+  const int kq = (K + 4 * kSmallWaves - 1) / (4 * kSmallWaves) * 4;
+  const int kb = wave * kq, ke = min(K, kb + kq);  // this wave's part of K
   auto opA = [&](int k) -> double {
-    if (ia >= M || k >= K) return 0.0;
+    if (ia >= M || k >= ke) return 0.0;
     return TA ? A[k + (int64_t)ia * lda] : A[ia + (int64_t)k * lda];
   };
   auto opB = [&](int k) -> double {
-    if (jb >= N || k >= K) return 0.0;
+    if (jb >= N || k >= ke) return 0.0;
     return TB ? B[jb + (int64_t)k * ldb] : B[k + (int64_t)jb * ldb];
   };
   v4d acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   constexpr int kSteps = 8;  // K steps of 4 per batch of loads
-  for (int k0 = 0; k0 < K; k0 += 4 * kSteps) {
+  for (int k0 = kb; k0 < ke; k0 += 4 * kSteps) {
     double a[kSteps], b[kSteps];
 #pragma unroll
     for (int u = 0; u < kSteps; ++u) {
@@ -593,6 +599,18 @@ __global__ __launch_bounds__(64) void k_gemm_small(int M, int N, int K, const do
       acc0 = mfma64(b[u], a[u], acc0);
       acc1 = mfma64(b[u + 1], a[u + 1], acc1);
     }
+  }
+  v4d acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = acc0[r] + acc1[r];
+  if (wave > 0) part[wave - 1][lane] = acc;
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int w = 0; w < kSmallWaves - 1; ++w) {
+    const v4d p = part[w][lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] += p[r];
   }
   const int row = m0 + li;
   if (row >= M) return;
@@ -607,7 +625,7 @@ __global__ __launch_bounds__(64) void k_gemm_small(int M, int N, int K, const do
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int col = n0 + lk + 4 * r;
-    if (col < N) C[row + (int64_t)col * ldc] = alpha * (acc0[r] + acc1[r]) + beta * old[r];
+    if (col < N) C[row + (int64_t)col * ldc] = alpha * acc[r] + beta * old[r];
   }
 }
 
@@ -619,10 +637,18 @@ __global__ void k_splitk_reduce(int M, int N, int S, const double* __restrict__ 
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx % M);
     const int64_t j = idx / M;
-    // Partials summed in order z = 0, 1, ...; loaded eight at a time so the
-    // loads are in flight together.
+    // Partials summed in order z = 0, 1, ...; loaded 32 (then eight) at a
+    // time so the loads are in flight together (the deep splits of the
+    // Gram matrices, 64 partials, wait for two round trips).
     double s = 0.0;
     int z = 0;
+    for (; z + 32 <= S; z += 32) {
+      double p[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) p[u] = P[(z + u) * zstride + idx];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) s += p[u];
+    }
     for (; z + 8 <= S; z += 8) {
       double p[8];
 #pragma unroll
@@ -715,10 +741,10 @@ hipError_t gemm(hipStream_t st, Prec prec, bool ta, bool tb, int M, int N, int K
   if (prec == PREC_FP64 && M <= kSmallMN && N <= kSmallMN && K <= kSmallK) {
     const dim3 grid((M + 15) / 16, (N + 15) / 16);
     const int slot = prof_mark(st, PC_GEMM_SMALL);
-    if (!ta && !tb) hipLaunchKernelGGL((k_gemm_small<false, false>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
-    else if (ta && !tb) hipLaunchKernelGGL((k_gemm_small<true, false>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
-    else if (!ta && tb) hipLaunchKernelGGL((k_gemm_small<false, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
-    else hipLaunchKernelGGL((k_gemm_small<true, true>), grid, dim3(64), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    if (!ta && !tb) hipLaunchKernelGGL((k_gemm_small<false, false>), grid, dim3(64 * kSmallWaves), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    else if (ta && !tb) hipLaunchKernelGGL((k_gemm_small<true, false>), grid, dim3(64 * kSmallWaves), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    else if (!ta && tb) hipLaunchKernelGGL((k_gemm_small<false, true>), grid, dim3(64 * kSmallWaves), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
+    else hipLaunchKernelGGL((k_gemm_small<true, true>), grid, dim3(64 * kSmallWaves), 0, st, M, N, K, A, lda, B, ldb, C, ldc, alpha, beta);
     prof_done(st, slot, PC_GEMM_SMALL, 2.0 * M * N * (double)K,
               8.0 * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2 : 1)));
     return hipGetLastError();
