@@ -218,14 +218,22 @@ SideCtx* side_ctx() {
 // side launch ends.  Short launches (about 130 us for the rank-b updates at
 // n = 8000) bound that wait, at some cost in tail effects of the side
 // products (measured: 1024 columns, 129.4 ms per factorization against
-// 134.6 ms uncut; 512-1536 within 1 ms of that).
+// 134.6 ms uncut; 512-1536 within 1 ms of that).  The reduction chunk of W =
+// X Vh is deeper when the main stream's updates are FP64: their longer
+// launches leave the side stream more room (n = 8000: 512 deep, 126.5 ms
+// against 128.4 ms at 256; 768 and 1024 deep in between), while with split
+// updates 256 and 512 measure the same within noise.
 #ifndef SIDE_CHUNK
 #define SIDE_CHUNK 256
+#endif
+#ifndef SIDE_CHUNK_FP64
+#define SIDE_CHUNK_FP64 512
 #endif
 #ifndef SIDE_COLS
 #define SIDE_COLS 1024
 #endif
 constexpr int kSideChunk = SIDE_CHUNK;  // reduction chunk of the thin products W = X Vh
+constexpr int kSideChunkFp64 = SIDE_CHUNK_FP64;  // the same with FP64 updates
 constexpr int kSideChunkUpd = 256;  // and of the rank-b updates X -= W2 Vh^T
 constexpr int kSideCols = SIDE_COLS;  // output columns per launch
 hipError_t gemm_side(hipStream_t st, bool ta, bool tb, int M, int N, int K, double alpha,
@@ -546,6 +554,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
   const int M = (int)m, N = (int)n, B = (int)b;
   const int Bp = (int)(b + p);    // samples per randomized step
   const int MN = std::max(M, N);  // leading dimension of the U / V stream products
+  const int side_chunk = pu == PREC_FP64 ? kSideChunkFp64 : kSideChunk;
   int* intsY = p > 0 ? (int*)(base + L.intsY) : nullptr;
   // Buffers of the pre-split operands (use_ps), and the product through them:
   // op(A) from A (rows M, rcontig when A is not transposed) if sa, op(B)
@@ -678,7 +687,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       if (formV) {  // V(:, J) = V(:, J) Vq, on the U / V stream
         double* VJ = V + (int64_t)r0 * ldv;
         HIPCHK(to_side(kVR + sl));
-        HIPCHK(gemm_side(ss, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, MN, kSideChunk));
+        HIPCHK(gemm_side(ss, false, false, N, B, Ni, 1.0, VJ, ldv, Vh, N, 0.0, Ws, MN, side_chunk));
         HIPCHK(gemm(ss, PREC_FP64, false, false, N, B, B, 1.0, Ws, MN, TwV, B, 0.0, W2s, MN, nullptr, 0));
         HIPCHK(gemm_side(ss, false, true, N, Ni, B, -1.0, W2s, MN, Vh, N, 1.0, VJ, ldv, kSideChunkUpd));
         HIPCHK(side_done(kVD + sl, &vpend[sl]));
@@ -699,7 +708,7 @@ int factor_core(int64_t m, int64_t n, int64_t b, int64_t p, int q, double* T, in
       if (formU && !econU) {  // on the U / V stream
         double* UI = U + (int64_t)r0 * ldu;
         HIPCHK(to_side(kUR + sl));
-        HIPCHK(gemm_side(ss, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, kSideChunk));
+        HIPCHK(gemm_side(ss, false, false, M, B, Mi, 1.0, UI, ldu, Uh, M, 0.0, Ws, MN, side_chunk));
         HIPCHK(gemm(ss, PREC_FP64, false, false, M, B, B, 1.0, Ws, MN, TwU, B, 0.0, W2s, MN, nullptr, 0));
         HIPCHK(gemm_side(ss, false, true, M, Mi, B, -1.0, W2s, MN, Uh, M, 1.0, UI, ldu, kSideChunkUpd));
         HIPCHK(side_done(kUD + sl, &upend[sl]));
