@@ -495,7 +495,12 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
 // read consecutive rows at each k); otherwise lanes go in 8 x 8 tiles, lane
 // l on kc = 8 kt + l mod 8, r = 8 rt + l / 8, so that eight lanes read 512
 // contiguous bytes of one column and eight lanes write 128 contiguous bytes.
-template <int NPC>
+// NS = S known at compile time (1..8; 0: S taken at run time): a chunk
+// inside X then issues all of its 8 NS loads before the sums, taken in the
+// same order (with a run-time S each partial's load waited for the one
+// before it, about 50 us per launch for the four partials of an 8000 x 256
+// sample).
+template <int NPC, int NS>
 __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, int64_t ldx,
                            int rcontig, int S, int64_t zs, uint4* __restrict__ out) {
   const int64_t total = (int64_t)Kc * R;
@@ -515,20 +520,54 @@ __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, i
       if (kc >= Kc || r >= R) continue;
     }
     const int64_t idx = (int64_t)kc * R + r;
+    double v[8];
+    if (NS > 0 && 8 * kc + 8 <= K) {
+      // Whole chunk inside X: every load first (four partials at a time),
+      // then the sums in order z = 0, 1, ... as below.
+      const int64_t o0 = rcontig ? r + (int64_t)(8 * kc) * ldx : 8 * kc + (int64_t)r * ldx;
+      const int64_t ke = rcontig ? ldx : 1;  // step between consecutive k
+      if constexpr (NS == 1) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = X[o0 + e * ke];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = 0.0;
+#pragma unroll
+        for (int z0 = 0; z0 < NS; z0 += 4) {
+          double p[4][8];
+#pragma unroll
+          for (int zz = 0; zz < 4; ++zz)
+            if (z0 + zz < NS) {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) p[zz][e] = X[(z0 + zz) * zs + o0 + e * ke];
+            }
+#pragma unroll
+          for (int zz = 0; zz < 4; ++zz)
+            if (z0 + zz < NS) {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) v[e] += p[zz][e];
+            }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * kc + e;
+        v[e] = 0.0;
+        if (k < K) {
+          const int64_t o = rcontig ? r + (int64_t)k * ldx : k + (int64_t)r * ldx;
+          if (S == 1) {
+            v[e] = X[o];
+          } else {  // split-K partials, summed in k_splitk_reduce's order
+            for (int z = 0; z < S; ++z) v[e] += X[z * zs + o];
+          }
+        }
+      }
+    }
     unsigned short h[8], m[8], l[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int k = 8 * kc + e;
-      double v = 0.0;
-      if (k < K) {
-        const int64_t o = rcontig ? r + (int64_t)k * ldx : k + (int64_t)r * ldx;
-        if (S == 1) {
-          v = X[o];
-        } else {  // split-K partials, summed in k_splitk_reduce's order
-          for (int z = 0; z < S; ++z) v += X[z * zs + o];
-        }
-      }
-      const float x = fl32(v);
+      const float x = fl32(v[e]);
       if constexpr (NPC == 3) {
         const Bf3 p = split3(x);
         h[e] = __builtin_bit_cast(unsigned short, p.h);
@@ -852,12 +891,27 @@ hipError_t presplit(hipStream_t st, Prec prec, int R, int K, const double* X, in
   if (R == 0 || kc == 0) return hipSuccess;
   const int64_t total = rcontig ? (int64_t)kc * R : (int64_t)((kc + 7) / 8) * ((R + 7) / 8) * 64;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
-  if (prec == PREC_BF16X6)
-    hipLaunchKernelGGL(k_presplit<3>, dim3(blocks), dim3(256), 0, st, R, K, kc, X, ldx,
-                       rcontig ? 1 : 0, S, zs, (uint4*)out);
-  else
-    hipLaunchKernelGGL(k_presplit<2>, dim3(blocks), dim3(256), 0, st, R, K, kc, X, ldx,
-                       rcontig ? 1 : 0, S, zs, (uint4*)out);
+  const int rc = rcontig ? 1 : 0;
+  auto go = [&](auto npc, auto ns) {
+    hipLaunchKernelGGL((k_presplit<decltype(npc)::value, decltype(ns)::value>), dim3(blocks),
+                       dim3(256), 0, st, R, K, kc, X, ldx, rc, S, zs, (uint4*)out);
+  };
+  auto by_s = [&](auto npc) {
+    using std::integral_constant;
+    switch (S) {
+      case 1: go(npc, integral_constant<int, 1>{}); break;
+      case 2: go(npc, integral_constant<int, 2>{}); break;
+      case 3: go(npc, integral_constant<int, 3>{}); break;
+      case 4: go(npc, integral_constant<int, 4>{}); break;
+      case 5: go(npc, integral_constant<int, 5>{}); break;
+      case 6: go(npc, integral_constant<int, 6>{}); break;
+      case 7: go(npc, integral_constant<int, 7>{}); break;
+      case 8: go(npc, integral_constant<int, 8>{}); break;
+      default: go(npc, integral_constant<int, 0>{}); break;
+    }
+  };
+  if (prec == PREC_BF16X6) by_s(std::integral_constant<int, 3>{});
+  else by_s(std::integral_constant<int, 2>{});
   return hipGetLastError();
 }
 
