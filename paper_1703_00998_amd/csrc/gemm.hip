@@ -495,11 +495,12 @@ __global__ __launch_bounds__(64 * WM * WN, WM * WN <= 8 ? 2 : 1) void k_gemm(
 // read consecutive rows at each k); otherwise lanes go in 8 x 8 tiles, lane
 // l on kc = 8 kt + l mod 8, r = 8 rt + l / 8, so that eight lanes read 512
 // contiguous bytes of one column and eight lanes write 128 contiguous bytes.
-// NS = S known at compile time (1..8; 0: S taken at run time): a chunk
-// inside X then issues all of its 8 NS loads before the sums, taken in the
-// same order (with a run-time S each partial's load waited for the one
-// before it, about 50 us per launch for the four partials of an 8000 x 256
-// sample).
+// NS = S known at compile time (1..8; 0: S taken at run time).  A chunk
+// inside X issues the loads of four partials (32 values) before summing
+// them, in the same order; with NS the partial loop unrolls completely.
+// (Summing element by element, each partial's load waited for the one
+// before it: about 50 us per launch for the four partials of an 8000 x 256
+// sample.)
 template <int NPC, int NS>
 __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, int64_t ldx,
                            int rcontig, int S, int64_t zs, uint4* __restrict__ out) {
@@ -521,7 +522,7 @@ __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, i
     }
     const int64_t idx = (int64_t)kc * R + r;
     double v[8];
-    if (NS > 0 && 8 * kc + 8 <= K) {
+    if (8 * kc + 8 <= K) {
       // Whole chunk inside X: every load first (four partials at a time),
       // then the sums in order z = 0, 1, ... as below.
       const int64_t o0 = rcontig ? r + (int64_t)(8 * kc) * ldx : 8 * kc + (int64_t)r * ldx;
@@ -530,23 +531,29 @@ __global__ void k_presplit(int R, int K, int Kc, const double* __restrict__ X, i
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = X[o0 + e * ke];
       } else {
+        const int ns = NS > 0 ? NS : S;
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = 0.0;
+        int z0 = 0;
 #pragma unroll
-        for (int z0 = 0; z0 < NS; z0 += 4) {
+        for (; z0 + 4 <= ns; z0 += 4) {
           double p[4][8];
 #pragma unroll
           for (int zz = 0; zz < 4; ++zz)
-            if (z0 + zz < NS) {
 #pragma unroll
-              for (int e = 0; e < 8; ++e) p[zz][e] = X[(z0 + zz) * zs + o0 + e * ke];
-            }
+            for (int e = 0; e < 8; ++e) p[zz][e] = X[(z0 + zz) * zs + o0 + e * ke];
 #pragma unroll
           for (int zz = 0; zz < 4; ++zz)
-            if (z0 + zz < NS) {
 #pragma unroll
-              for (int e = 0; e < 8; ++e) v[e] += p[zz][e];
-            }
+            for (int e = 0; e < 8; ++e) v[e] += p[zz][e];
+        }
+#pragma unroll
+        for (; z0 < ns; ++z0) {
+          double p[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) p[e] = X[z0 * zs + o0 + e * ke];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] += p[e];
         }
       }
     } else {

@@ -5,7 +5,7 @@ operands, and the MFMAs take them in the same order, so a factorization
 through them must equal, to the bit, the same factorization run with a
 workspace sized for FP64 (no room for the buffers, so the loaders split the
 operands themselves).  Shapes span 64 x 64 and 128 x 128 product tiles, a
-ragged last block and the sampling products' split-K.  The oracle parity of
+ragged last block and the sampling products' split-K, 1 to 45 partials.  The oracle parity of
 these paths is covered by test_gpu_split_oracle and test_gpu_factor."""
 import ctypes
 
@@ -32,6 +32,11 @@ CASES = [  # m, n, b, q, prec
     (2600, 2600, 128, 1, "bf16x3_bf16x6"),
     (2600, 2500, 128, 2, "bf16x3_fp32"),
     (3000, 2000, 256, 1, "bf16x3"),
+    # thin samples of a tall matrix: the sampling products' split-K takes 8
+    # partials in the first steps, then deep splits of 19 to 45 once the
+    # sample has at most 32 output tiles, and the row count leaves a ragged
+    # last chunk of 8 in the reduction
+    (5004, 3000, 64, 1, "bf16x3_bf16x6"),
 ]
 
 
